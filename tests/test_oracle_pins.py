@@ -1,0 +1,419 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test names the passage it follows.  None compares the oracle with
+itself: closed forms, invariants, special cases reducing to textbook results
+and brute force between the two independent oracle tiers.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special
+
+import synth
+from oracle import o1_dense as o1
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+rng0 = np.random.default_rng(1234)
+
+
+def _random_states(n=40, du=0.1, df=1e-2, seed=0):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.9, 1.1, n)
+    u = rng.uniform(-du, du, (n, 3))
+    f = o1.equilibrium_product(rho, u) + rng.normal(0.0, df, (n, 27))
+    return f
+
+
+# ---- lattice ------------------------------------------------------------------
+
+def test_weights_match_textbook_golden():
+    """D3Q27 weights (golden file, textbook values) and the lattice isotropy
+    sums sum w = 1, sum w c c = cs^2 I that Eq. (3) relies on."""
+    table = {}
+    with open(os.path.join(GOLDEN, "d3q27_weights.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, c2, count, w = line.split()
+            num, den = w.split("/")
+            table[int(c2)] = (int(count), float(num) / float(den))
+    c2 = (o1.C ** 2).sum(axis=1)
+    for k, (count, w) in table.items():
+        assert np.count_nonzero(c2 == k) == count
+        assert np.allclose(o1.W[c2 == k], w, rtol=0, atol=1e-16)
+    assert abs(o1.W.sum() - 1.0) < 1e-15
+    second = np.einsum("a,ai,aj->ij", o1.W, o1.C, o1.C)
+    assert np.allclose(second, np.eye(3) / 3.0, atol=1e-16)
+    assert all(np.array_equal(o1.C[o1.OPP[a]], -o1.C[a]) for a in range(27))
+
+
+# ---- P1-P5: closed forms and invariants of Eqs. (3), (6)-(8) -----------------------
+
+def test_P1_series_equilibrium_equals_product_form():
+    """Eq. (3) with the full D3Q27 expansion (Sec. 2.1.3) equals the product of
+    one-dimensional factors."""
+    rng = np.random.default_rng(1)
+    rho = rng.uniform(0.8, 1.2, 64)
+    u = rng.uniform(-0.2, 0.2, (64, 3))
+    a = o1.equilibrium_series(rho, u)
+    b = o1.equilibrium_product(rho, u)
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_P1b_equilibrium_moments():
+    """The equilibrium reproduces rho and rho u (Eqs. (4)-(5))."""
+    rng = np.random.default_rng(2)
+    rho = rng.uniform(0.8, 1.2, 16)
+    u = rng.uniform(-0.2, 0.2, (16, 3))
+    feq = o1.equilibrium_series(rho, u)
+    assert np.allclose(feq.sum(axis=1), rho, atol=1e-14, rtol=0)
+    assert np.allclose(feq @ o1.C, rho[:, None] * u, atol=1e-14, rtol=0)
+
+
+def test_P2_central_moments_of_equilibrium():
+    """T f_eq = (rho, 0, ..., 0): Eqs. (7)-(8a,b)."""
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.8, 1.2, 32)
+    u = rng.uniform(-0.2, 0.2, (32, 3))
+    m = np.einsum("nma,na->nm", o1.central_transform(u), o1.equilibrium_series(rho, u))
+    assert np.max(np.abs(m[:, 0] - rho)) < 1e-14
+    assert np.max(np.abs(m[:, 1:])) < 1e-14
+
+
+def test_P2b_second_order_second_rate_only_changes_viscous_moments():
+    """Only the six second-order rows carry s2 (Sec. 2.1.3): with every other rate
+    equal to 1 and s2 = 1, the post-collision central moments vanish except
+    order 0 (rho) and order 1 (rho g / 2, the forcing reading)."""
+    f = _random_states(8)
+    g = (1e-4, -2e-4, 3e-4)
+    fp, rho, _, u = o1.collide(f, 1.0, (1.0, 1.0, 1.0, 1.0), g)
+    m = np.einsum("nma,na->nm", o1.central_transform(u), fp)
+    assert np.allclose(m[:, 0], rho, atol=1e-14)
+    for d, idx in enumerate((1, 3, 9)):
+        assert np.allclose(m[:, idx], 0.5 * rho * g[d], atol=1e-15)
+    rest = [k for k in range(27) if k not in (0, 1, 3, 9)]
+    assert np.max(np.abs(m[:, rest])) < 1e-14
+
+
+def test_P3_transform_invertible_and_factored_equals_dense(o2lib):
+    """T is invertible for any u, and the factored per-axis transforms of tier O2
+    give the same collision as the dense linear solve of tier O1."""
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-0.3, 0.3, (16, 3))
+    T = o1.central_transform(u)
+    assert np.min(np.abs(np.linalg.det(T))) > 1e-6
+    case = synth.periodic_box_case(4, 2, 2, tau=0.7, g=(1e-4, 2e-4, -1e-4),
+                                   rates=(1.3, 0.7, 1.6, 1.1))
+    sim = o2lib.O2Sim(case, nthreads=1)
+    f = _random_states(sim.n, seed=5)
+    sim.f[...] = f
+    sim.collide()
+    fp, _, _, _ = o1.collide(f, case.tau, case.rates, case.g)
+    assert np.max(np.abs(sim.fpost - fp)) < 1e-14
+
+
+def test_P4_equal_rates_reduce_to_bgk(o2lib):
+    """All rates equal to 1/tau: CHM-MRT becomes the BGK operator of Eq. (2),
+    in both oracle tiers."""
+    f = _random_states(32, seed=6)
+    tau = 0.73
+    fp, rho, _, u = o1.collide(f, tau, (1 / tau,) * 4, (0.0, 0.0, 0.0))
+    feq = o1.equilibrium_product(rho, u)
+    bgk = f + (feq - f) / tau
+    assert np.max(np.abs(fp - bgk)) < 1e-14
+    case = synth.periodic_box_case(4, 4, 2, tau=tau, rates=(1 / tau,) * 4)
+    sim = o2lib.O2Sim(case, nthreads=1)
+    sim.f[...] = f
+    sim.collide()
+    assert np.max(np.abs(sim.fpost - bgk)) < 1e-14
+
+
+def test_P5_collision_conserves_mass_and_adds_rho_g():
+    """sum f* = sum f and sum c f* = sum c f + rho g (forcing reading)."""
+    f = _random_states(32, seed=7)
+    g = np.array([3e-4, -1e-4, 2e-4])
+    fp, rho, j, _ = o1.collide(f, 0.9, (1.2, 0.8, 1.5, 0.6), g)
+    assert np.max(np.abs(fp.sum(1) - f.sum(1))) < 1e-14
+    assert np.max(np.abs(fp @ o1.C - (j + rho[:, None] * g[None, :]))) < 1e-14
+
+
+# ---- P6-P9: whole-step invariants ------------------------------------------------
+
+def _closed_random_case(seed):
+    case = synth.random_tiny_case(seed)
+    case.mask[case.mask >= 2] = synth.SOLID
+    case.inlet = None
+    return case
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_P6_rest_state_is_bitwise_fixed_point(o2lib, seed):
+    """With g = 0 the rest equilibrium f = w is unchanged by collision,
+    bounce-back and periodic streaming (to FP64 rounding of the unshifted
+    oracle arithmetic)."""
+    case = _closed_random_case(seed)
+    case.g = (0.0, 0.0, 0.0)
+    sim = o2lib.O2Sim(case, nthreads=1)
+    f0 = sim.f.copy()
+    sim.run(5)
+    assert np.max(np.abs(sim.f - f0)) < 1e-16
+    st = o1.run(case, 3)
+    fl = st.fluid
+    assert np.max(np.abs(st.f[fl[:, 0], fl[:, 1], fl[:, 2]] - o1.W[None, :])) < 1e-15
+
+
+def test_P6b_uniform_flow_in_periodic_box_is_fixed_point(o2lib):
+    case = synth.periodic_box_case(5, 4, 3, tau=0.6, rates=(1.1, 0.9, 1.4, 0.7))
+    sim = o2lib.O2Sim(case, nthreads=1)
+    u = np.tile([[0.05, -0.03, 0.02]], (sim.n, 1))
+    sim.f[...] = o1.equilibrium_product(np.ones(sim.n), u)
+    f0 = sim.f.copy()
+    sim.run(10)
+    assert np.max(np.abs(sim.f - f0)) < 1e-15
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_P7_zero_rates_make_a_step_a_permutation(o2lib, seed):
+    """With every rate of order >= 2 set to 0 and g = 0 the collision is the
+    identity, so a step only permutes the population values (streaming and
+    bounce-back, Eqs. (1) and (9)); sorted values agree to FP64 rounding (rho ~ 13 here) while
+    distinct values are ~1e-4 apart."""
+    case = _closed_random_case(seed)
+    case.g = (0.0, 0.0, 0.0)
+    sim = o2lib.O2Sim(case, nthreads=1, rates5=(0.0,) * 5)
+    rng = np.random.default_rng(seed)
+    sim.f[...] = rng.random((sim.n, 27))
+    before = np.sort(sim.f.ravel())
+    sim.run(3)
+    assert np.max(np.abs(np.sort(sim.f.ravel()) - before)) < 1e-13
+
+
+def test_P8_pipe_mass_conserved_2000_steps(o2lib):
+    """Closed periodic pipe (64x24x24, R = 10, g = 1e-6, tau = 0.8): mass is
+    conserved over 2000 steps (collision conserves mass, halfway bounce-back
+    returns every population).  The bound is FP64 rounding of the unshifted
+    oracle arithmetic, about 1e-16 per node update over 4e7 updates."""
+    case = synth.pipe_case()
+    sim = o2lib.O2Sim(case, nthreads=8)
+    m0 = sim.f.sum()
+    mon = sim.run(2000)
+    assert sim.n == 20224
+    assert abs(mon[0] - m0) / m0 < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 4, 5])
+def test_P8b_open_system_mass_balance(o2lib, seed):
+    """With inlet and outlet ghosts, M(t+1) - M(t) equals the boundary flux of
+    that step exactly (to rounding), in both tiers."""
+    case = synth.random_tiny_case(seed)
+    sim = o2lib.O2Sim(case, nthreads=1)
+    st = o1.O1State(case)
+    m_prev = sim.f.sum()
+    for _ in range(10):
+        mon = sim.run(1)
+        assert abs(mon[0] - m_prev - (mon[7] + mon[8])) < 1e-13 * mon[0]
+        m_prev = mon[0]
+        mprev1 = st.f.sum()
+        o1.step(st)
+        assert abs(st.monitors[0] - mprev1 - (st.monitors[7] + st.monitors[8])) < 1e-13 * mprev1
+
+
+def test_P9_periodic_box_momentum_grows_as_M_g_t(o2lib):
+    case = synth.periodic_box_case(6, 5, 4, tau=0.9, g=(2e-5, -1e-5, 3e-5),
+                                   rates=(1.2, 0.8, 1.5, 1.7))
+    sim = o2lib.O2Sim(case, nthreads=2)
+    for t in (7, 50):
+        mon = sim.run(t - sim.t)
+        expect = mon[0] * np.asarray(case.g) * t
+        assert np.max(np.abs(mon[1:4] - expect)) < 1e-12 * np.max(np.abs(expect)) + 1e-16
+
+
+# ---- P10-P13: closed-form flows ---------------------------------------------------
+
+def _shear_rate_error(o2lib, L, tau, rates):
+    case = synth.periodic_box_case(4, L, 1, tau=tau, rates=rates)
+    sim = o2lib.O2Sim(case, nthreads=4)
+    y = sim.coords[:, 1]
+    shape = np.sin(2 * np.pi * y / L)
+    u0 = np.zeros((sim.n, 3))
+    u0[:, 0] = 1e-3 * shape
+    sim.f[...] = o1.equilibrium_product(np.ones(sim.n), u0)
+    amps = []
+    t1, t2 = (L * L) // 10, (3 * L * L) // 10
+    for t in (t1, t2):
+        sim.run(t - sim.t)
+        _, u = sim.macroscopic()
+        amps.append((u[:, 0] * shape).sum() / (shape * shape).sum())
+    rate = -math.log(amps[1] / amps[0]) / (t2 - t1)
+    return rate / (case.nu * (2 * math.pi / L) ** 2) - 1.0
+
+
+def test_P10_shear_wave_decays_at_viscous_rate(o2lib):
+    """A sinusoidal shear wave decays as exp(-nu k^2 t) with nu = (tau - 1/2)/3,
+    which ties the second-order rate 1/tau to the viscosity (Sec. 2.1.3).  The
+    relative rate error is a truncation error of order k^2: small at L = 32 and
+    about four times smaller at L = 64."""
+    for tau, rates in ((0.8, (1.0,) * 4), (0.6, (1.4, 0.9, 1.2, 1.0))):
+        e32 = _shear_rate_error(o2lib, 32, tau, rates)
+        e64 = _shear_rate_error(o2lib, 64, tau, rates)
+        assert abs(e32) < 5e-3
+        assert abs(e64) < abs(e32) / 3.0
+
+
+def _poiseuille_startup(r, t, R, nu, g):
+    lam = scipy.special.jn_zeros(0, 60)
+    u = g * (R * R - r * r) / (4 * nu)
+    for l in lam:
+        u = u - 2 * g * R * R / nu * scipy.special.j0(l * r / R) / (l ** 3 * scipy.special.j1(l)) \
+            * np.exp(-l * l * nu * t / (R * R))
+    return u
+
+
+def _pipe_error(o2lib, R, steps, nx=4):
+    n = int(2 * R + 4)
+    c = synth.pipe_case(nx=nx, ny=n, nz=n, radius=R, center=((n - 1) / 2, (n - 1) / 2))
+    sim = o2lib.O2Sim(c, nthreads=8)
+    sim.run(steps)
+    _, u = sim.macroscopic()
+    y = sim.coords[:, 1] - (n - 1) / 2
+    z = sim.coords[:, 2] - (n - 1) / 2
+    ua = _poiseuille_startup(np.sqrt(y * y + z * z), steps, R, c.nu, 1e-6)
+    return np.sqrt(((u[:, 0] - ua) ** 2).sum() / (ua ** 2).sum()), np.abs(u[:, 1:]).max()
+
+
+def test_P11_pipe_poiseuille_and_staircase_trend(o2lib):
+    """Config-1 pipe against the Poiseuille start-up series: a few per cent L2
+    error from the staircase wall at R = 10, shrinking at least as 1/R at R = 20."""
+    e10, cross10 = _pipe_error(o2lib, 10, 2000)
+    e20, _ = _pipe_error(o2lib, 20, 8000)
+    assert e10 < 0.05
+    assert e20 < e10 / 2.0
+    assert cross10 < 1e-14
+
+
+def test_P13_womersley_pipe(o2lib):
+    """Periodic pipe driven by g(t) = g0 + g1 cos(omega t) at Womersley number 3
+    (the paper's pulsatile case has Wo = 2.54, Sec. 2.2.2): after five periods
+    the profile follows the Womersley closed form to the staircase error."""
+    R, n, tau = 10.0, 24, 0.8
+    nu = (tau - 0.5) / 3
+    w = 9.0 * nu / R ** 2
+    g0 = g1 = 1e-6
+    c = synth.pipe_case(nx=4, ny=n, nz=n, radius=R, center=((n - 1) / 2, (n - 1) / 2), g=g0, tau=tau)
+    sim = o2lib.O2Sim(c, nthreads=8, g_time=((g0, 0, 0), (g1, 0, 0), w))
+    period = 2 * math.pi / w
+    sim.run(int(round(5 * period)))
+    y = sim.coords[:, 1] - (n - 1) / 2
+    z = sim.coords[:, 2] - (n - 1) / 2
+    r = np.sqrt(y * y + z * z)
+    worst = 0.0
+    for _ in range(8):
+        sim.run(int(round(period / 8)))
+        t = sim.t
+        _, u = sim.macroscopic(g=(g0 + g1 * math.cos(w * t), 0, 0))
+        ua = o1.womersley_speed(r, t, R, nu, g0, g1, w)
+        worst = max(worst, math.sqrt(((u[:, 0] - ua) ** 2).sum() / (ua ** 2).sum()))
+    assert worst < 0.06
+
+
+def test_womersley_profile_solves_its_ode():
+    """The inlet profile solves i w U = G1 + nu (U'' + U'/r) for its oscillating
+    part, vanishes at the wall and reduces to Poiseuille for w = 0."""
+    R, nu, w, G1 = 12.0, 0.025, 2 * math.pi / 4000, 2e-5
+    r = np.linspace(0.5, R - 0.5, 200)
+    h = 1e-3
+    # complex amplitude = value at t=0 minus i * value at a quarter period
+    def amp(rr):
+        a = o1.womersley_speed(rr, 0.0, R, nu, 0.0, G1, w)
+        b = o1.womersley_speed(rr, math.pi / (2 * w), R, nu, 0.0, G1, w)
+        return a - 1j * b
+    U = amp(r)
+    d2 = (amp(r + h) - 2 * U + amp(r - h)) / h ** 2
+    d1 = (amp(r + h) - amp(r - h)) / (2 * h)
+    res = 1j * w * U - G1 - nu * (d2 + d1 / r)
+    assert np.max(np.abs(res)) < 1e-6 * G1 + 1e-12
+    assert abs(amp(np.array([R - 1e-9]))[0]) < 1e-9
+    steady = o1.womersley_speed(r, 0.0, R, nu, 3e-5, 0.0, 0.0)
+    assert np.allclose(steady, 3e-5 * (R * R - r * r) / (4 * nu), rtol=1e-14)
+
+
+def test_oracle_bessel_series_matches_scipy(o2lib):
+    """Tier O2 evaluates J0 by its power series; tier O1 uses scipy.  Their inlet
+    velocities agree (checked through one streaming step with only inlet links)."""
+    case = synth.random_tiny_case(11)
+    sim = o2lib.O2Sim(case, nthreads=1)
+    st = o1.O1State(case)
+    for _ in range(3):
+        sim.run(1)
+        o1.step(st)
+    fl = st.fluid
+    assert np.max(np.abs(st.f[fl[:, 0], fl[:, 1], fl[:, 2]] - sim.f)) < 1e-14
+
+
+# ---- P14: acoustic scaling --------------------------------------------------------
+
+def test_P14_acoustic_scaling_matches_paper_pair():
+    """Sec. 2.2.3 prints tau = 0.506 (dx 1e-4, dt 5e-6) and 0.503 (dx 2e-4,
+    dt 1e-5): tau - 1/2 halves when dx and dt double.  The aneurysm cases follow
+    the same rule between 128^3, 256^3 and 512^3."""
+    vals = {}
+    with open(os.path.join(GOLDEN, "acoustic_scaling.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    assert vals["coarse_dt"] / vals["fine_dt"] == vals["coarse_dx"] / vals["fine_dx"] == 2.0
+    assert abs((vals["coarse_tau"] - 0.5) - (vals["fine_tau"] - 0.5) / 2) < 1e-12
+    taus = {}
+    for n in (128, 256):
+        c = synth.aneurysm_case(n, seed=0)
+        taus[n] = c.tau
+    taus[512] = 0.5 + 2 * (taus[256] - 0.5)
+    assert abs((taus[128] - 0.5) - (taus[256] - 0.5) / 2) < 1e-15
+    assert abs(taus[256] - 0.575398) < 1e-6
+
+
+# ---- P15: brute force between the tiers -------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_P15_dense_and_factored_oracles_agree(o2lib, seed):
+    """Tiny random masks with walls, periodic axes, inlet and outlet ghosts,
+    random rates, force and inlet: O1 (dense definition) == O2 (factored)."""
+    case = synth.random_tiny_case(seed)
+    st = o1.run(case, 20)
+    sim = o2lib.O2Sim(case, nthreads=2)
+    sim.run(20)
+    fl = st.fluid
+    assert np.max(np.abs(st.f[fl[:, 0], fl[:, 1], fl[:, 2]] - sim.f)) < 1e-13
+    assert np.max(np.abs(st.monitors - sim.monitors)) < 1e-12
+
+
+def test_oracle_catches_planted_mistakes(o2lib, monkeypatch):
+    """A dropped forcing term or a wrong order-to-rate assignment changes the
+    result far above rounding, so the brute-force pin P15 would catch it
+    (planted in tier O1, on the CPU)."""
+    case = synth.random_tiny_case(0)
+    ref = o1.run(case, 5).f.copy()
+    # 1) drop the (I - S/2) F forcing term
+    orig = o1.collide
+
+    def no_force(f, tau, rates, g):
+        return orig(f, tau, rates, (0.0, 0.0, 0.0))
+    monkeypatch.setattr(o1, "collide", no_force)
+    bad = o1.run(case, 5).f
+    monkeypatch.setattr(o1, "collide", orig)
+    assert np.max(np.abs(bad - ref)) > 1e-8
+    # 2) wrong order -> rate assignment (swap orders 3 and 4)
+    orig_rates = o1.relaxation_rates
+
+    def swapped(tau, rates):
+        r = list(rates)
+        r[0], r[1] = r[1], r[0]
+        return orig_rates(tau, r)
+    monkeypatch.setattr(o1, "relaxation_rates", swapped)
+    bad = o1.run(case, 5).f
+    monkeypatch.setattr(o1, "relaxation_rates", orig_rates)
+    assert np.max(np.abs(bad - ref)) > 1e-8
