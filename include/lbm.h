@@ -1,0 +1,196 @@
+/*
+ * lbm.h -- C ABI of the MI355X D3Q27 CHM-MRT lattice Boltzmann library.
+ *
+ * What the library computes: the lattice Boltzmann evolution equation (Eq. (1))
+ * with the central Hermite moment multiple-relaxation-time collision (CHM-MRT,
+ * Eq. (6)) and the full-expansion equilibrium (Eq. (3) with the sixth-order
+ * D3Q27 expansion of Sec. 2.1.3, whose central moments are (rho, 0, ..., 0),
+ * Eq. (8)), on a voxelized vessel: halfway bounce-back walls (Eq. (9) at
+ * q = 1/2), a velocity inlet and a pressure outlet built from the bounce-back
+ * family (Sec. 2.1.2).  One step is one fused pull-scheme kernel over the list
+ * of fluid nodes.
+ *
+ * Conventions for every function:
+ *  - Return value: LBM_OK (0) or a negative LBM_E* code.  Nothing throws or
+ *    aborts across the ABI; lbm_last_error() returns a message for the last
+ *    failure of the calling thread.
+ *  - "host" pointers are read or written during the call and may be freed
+ *    afterwards.  "device" pointers are GPU global memory that the caller owns
+ *    and keeps alive for as long as the library may use them.
+ *  - Device memory: the library never allocates GPU memory.  The caller asks
+ *    for the size (lbm_device_bytes), allocates it (for example as a torch
+ *    uint8 tensor) and attaches it (lbm_attach_device).
+ *  - Work is enqueued on the HIP stream given at creation and is asynchronous
+ *    unless the function says it synchronizes.
+ *  - A domain is not thread-safe; different domains are independent.
+ *
+ * Units: lattice units (dx = dt = 1), sound speed squared 1/3, kinematic
+ * viscosity nu = (tau - 1/2) / 3.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_domain lbm_domain;   /* opaque, library-owned */
+typedef struct lbm_batch lbm_batch;     /* opaque, library-owned */
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument */
+    LBM_ENOMEM = -2,     /* host allocation failed or device buffer too small */
+    LBM_EDEVICE = -3,    /* a HIP call failed (message in lbm_last_error) */
+    LBM_EUNSTABLE = -4,  /* non-finite monitor values: the run diverged */
+    LBM_ESTATE = -5      /* call out of order (e.g. step before attach) */
+};
+
+/* Population storage.  Every storage type holds the shifted populations
+ * f - w_alpha (rest state = 0).  F64 and F32 compute in their own precision;
+ * F16S and BF16S store IEEE half / bfloat16 (round to nearest even, half
+ * subnormals kept) and compute in FP32.  Boundary, force and monitor sums
+ * are accumulated in FP64 for every storage type. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
+
+/* Mask cell types: mask[(z * ny + y) * nx + x]. */
+enum { LBM_SOLID = 0, LBM_FLUID = 1, LBM_INLET = 2, LBM_OUTLET = 3 };
+
+/* Periodic axes. */
+enum { LBM_PERIODIC_X = 1, LBM_PERIODIC_Y = 2, LBM_PERIODIC_Z = 4 };
+
+/* Collision parameters (Eq. (6), Sec. 2.1.3).  The six second-order central
+ * Hermite moments relax with rate 1/tau (tau > 1/2 sets the viscosity); the
+ * moments of orders 3, 4, 5 and 6 relax with the free rates s[0..3], each in
+ * (0, 2).  g is a constant body acceleration (force density rho g); it enters
+ * the velocity with the half-step shift u = (j + rho g / 2) / rho and the
+ * first-order central moments after collision are rho g / 2.  struct_size must
+ * be sizeof(lbm_params). */
+typedef struct {
+    uint32_t struct_size;
+    double tau;
+    double s[4];
+    double g[3];
+} lbm_params;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Build a domain from a voxel mask (host, copied).
+ * nx, ny, nz in [1, 1023]; mask values in {SOLID, FLUID, INLET, OUTLET};
+ * at least one FLUID cell.  A fluid node x pulls direction alpha from
+ * x - c_alpha: from a FLUID cell by streaming, from a SOLID cell or from
+ * outside the box on a non-periodic axis by halfway bounce-back, from an
+ * INLET ghost by the velocity inlet rule and from an OUTLET ghost by the
+ * pressure outlet rule.  periodic_bits: LBM_PERIODIC_* flags.  storage:
+ * LBM_F64 / F32 / F16S / BF16S.  hip_stream: hipStream_t (NULL = default).
+ * Fluid nodes are numbered in x-fastest order (x, then y, then z).
+ * Errors: EINVAL for bad sizes, values or flags; ENOMEM on host allocation. */
+int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
+                      int storage, void* hip_stream, lbm_domain** out);
+
+/* Device bytes the caller must provide to lbm_attach_device. */
+int lbm_device_bytes(const lbm_domain* dom, size_t* bytes);
+
+/* Attach caller-owned device memory (at least lbm_device_bytes, 256-byte
+ * aligned) and upload the node tables (asynchronous on the stream).  The
+ * memory must outlive the domain.  ENOMEM if too small, EINVAL if misaligned. */
+int lbm_attach_device(lbm_domain* dom, void* dev_ptr, size_t bytes);
+
+/* Number of fluid nodes. */
+int lbm_fluid_count(const lbm_domain* dom, int64_t* n);
+
+/* Coordinates of the fluid nodes in library order: host int32 [n][3] = (x, y, z). */
+int lbm_fluid_coords(const lbm_domain* dom, int32_t* xyz);
+
+/* Set tau, the free rates and the body force (Eq. (6), Sec. 2.1.3).
+ * EINVAL unless tau > 1/2, every s in (0, 2), all values finite. */
+int lbm_set_params(lbm_domain* dom, const lbm_params* p);
+
+/* Velocity inlet on the INLET ghost cells: the wall velocity of a link is
+ * u_w = axis * U(r, t) at the link midpoint, where r is the distance from the
+ * line through `center` along `axis` and U is the Womersley profile
+ * U = G0 (R^2 - r^2) / (4 nu) + Re{ G1 / (i omega) [1 - J0(i^{3/2} a r / R)
+ * / J0(i^{3/2} a)] e^{i omega t} }, a = R sqrt(omega / nu), U = 0 for r >= R,
+ * and omega = 0 gives the steady Poiseuille profile.  The incoming population
+ * is f_a(x, t+1) = f*_abar(x, t) + f_eq_a(1, u_w) - f_eq_abar(1, u_w)
+ * (moving-wall bounce-back) with t the time of the populations being
+ * streamed.  axis must be non-zero, radius > 0, values finite. */
+int lbm_set_inlet_womersley(lbm_domain* dom, const double axis[3], const double center[3],
+                            double radius, double G0, double G1, double omega);
+
+/* Pressure outlet on the OUTLET ghost cells (default rho_out = 1, zero gauge
+ * pressure): f_a(x, t+1) = -f*_abar(x, t) + f_eq_a(rho_out, u(x, t))
+ * + f_eq_abar(rho_out, u(x, t)) (anti-bounce-back), with u(x, t) the
+ * velocity of the node's last collision.  EINVAL unless rho_out > 0. */
+int lbm_set_outlet_pressure(lbm_domain* dom, double rho_out);
+
+/* Initial state at t = 0: f(0) = f_eq(rho, u) (product form of Eq. (3)),
+ * followed by the first collision.  rho (device double [n]) and u (device
+ * double [3][n]) may be NULL for rest (rho = 1, u = 0).  Needs attach and
+ * params (ESTATE otherwise). */
+int lbm_init_equilibrium(lbm_domain* dom, const double* rho, const double* u);
+
+/* Advance nsteps >= 0 time steps (asynchronous).  Each step pulls
+ * f(x, t+1) from the post-collision populations of step t, applies the
+ * boundary rules, computes rho and u, collides (Eq. (6)) and stores the
+ * post-collision populations; the same kernel writes per-block FP64 monitor
+ * partials.  ESTATE before lbm_init_equilibrium. */
+int lbm_step(lbm_domain* dom, int nsteps);
+
+/* Current time index t (number of steps since initialisation). */
+int lbm_time(const lbm_domain* dom, int64_t* t);
+
+/* rho(t) (device double [n]) and u(t) (device double [3][n], component-major)
+ * of the current state, in fluid-node order (Eqs. (4)-(5) with the half-force
+ * velocity shift).  Either pointer may be NULL.  Asynchronous. */
+int lbm_moments(lbm_domain* dom, double* rho, double* u);
+
+/* Time averaging of u (FP64 accumulator in the attached memory).
+ * op = LBM_AVG_RESET clears it, LBM_AVG_ACCUMULATE adds u(t), LBM_AVG_READ
+ * writes the mean to u_avg (device double [3][n]; ESTATE if nothing was
+ * accumulated).  Asynchronous. */
+enum { LBM_AVG_RESET = 0, LBM_AVG_ACCUMULATE = 1, LBM_AVG_READ = 2 };
+int lbm_average(lbm_domain* dom, int op, double* u_avg);
+
+/* Monitors of the last step (host double[10]); synchronizes the stream.
+ * out = { mass sum rho, momentum sum j (3), wall force (3), inlet mass flux,
+ * outlet mass flux, t }.  The wall force is the momentum the walls receive,
+ * sum over wall links of 2 f*_abar c_abar; a flux is the mass a boundary
+ * added in that step, so M(t) - M(t-1) = inlet + outlet flux.  Sums are FP64
+ * in a fixed order (deterministic).  EUNSTABLE if any value is not finite;
+ * ESTATE before the first step. */
+int lbm_monitors(lbm_domain* dom, double out[10]);
+
+/* Post-collision shifted populations f*(t) - w as FP64 (device double
+ * [27][n], direction-major, alpha = 9 (cz+1) + 3 (cy+1) + (cx+1)).  Exact
+ * conversion from the storage type.  Asynchronous. */
+int lbm_read_populations(lbm_domain* dom, double* f_dev);
+
+/* Checkpoint: raw state (populations in storage format, outlet velocities,
+ * time).  With host == NULL, *bytes receives the size; otherwise *bytes must
+ * be at least that size.  Synchronizes the stream. */
+int lbm_get_state(lbm_domain* dom, void* host, size_t* bytes);
+
+/* Restore a checkpoint taken from a domain with the same mask and storage.
+ * EINVAL if the header does not match.  Synchronizes the stream. */
+int lbm_set_state(lbm_domain* dom, const void* host, size_t bytes);
+
+/* Host-side evaluation of the inlet speed U(r, t) used by the velocity inlet
+ * (same profile as lbm_set_inlet_womersley, with viscosity nu).  Pure host
+ * computation; usable without a GPU.  EINVAL for radius <= 0, nu <= 0 or
+ * non-finite r, t. */
+int lbm_inlet_profile(double r, double t, double radius, double nu, double G0, double G1,
+                      double omega, double* speed);
+
+/* Free the host side of the domain (the caller frees the device memory). */
+void lbm_destroy(lbm_domain* dom);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,646 @@
+// C ABI of the lattice Boltzmann library: domain construction from a voxel
+// mask, parameter validation, inlet profile coefficients, device-memory
+// layout, and the launch sequence of the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using lbm::BcLink;
+using lbm::SpecialNode;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+size_t storage_bytes(int storage) {
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16S: return 2;
+        case LBM_BF16S: return 2;
+        default: return 0;
+    }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Complex Bessel function J0 by its power series sum_k (-z^2/4)^k / (k!)^2
+// (converges for every z; the arguments here have |z| < 10).
+std::complex<double> bessel_j0(std::complex<double> z) {
+    const std::complex<double> q = -z * z / 4.0;
+    std::complex<double> term = 1.0, sum = 1.0;
+    for (int k = 1; k < 300; ++k) {
+        term *= q / (double(k) * double(k));
+        sum += term;
+        if (std::abs(term) < 1e-18 * std::abs(sum)) break;
+    }
+    return sum;
+}
+
+// Steady part a0 and complex oscillating amplitude a1 of the Womersley speed
+// U(r, t) = a0 + Re(a1 e^{i omega t}) in a pipe of radius R.
+void womersley_coeffs(double r, double R, double nu, double G0, double G1, double omega,
+                      double* a0, std::complex<double>* a1) {
+    *a0 = 0.0;
+    *a1 = 0.0;
+    if (!(r < R)) return;
+    *a0 = G0 * (R * R - r * r) / (4.0 * nu);
+    if (omega != 0.0 && G1 != 0.0) {
+        const double alpha = R * std::sqrt(omega / nu);
+        const std::complex<double> i32 = std::polar(1.0, 0.75 * M_PI);   // i^{3/2}
+        const std::complex<double> ratio = bessel_j0(i32 * (alpha * r / R)) / bessel_j0(i32 * alpha);
+        *a1 = G1 / (std::complex<double>(0.0, 1.0) * omega) * (1.0 - ratio);
+    }
+}
+
+bool finite_all(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct lbm_domain {
+    int nx = 0, ny = 0, nz = 0;
+    unsigned periodic = 0;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+
+    int64_t n = 0;
+    int npad = 0;
+    int W = 0;
+    int rows = 0;
+    int nblocks = 0, blocks_per_xcd = 0;
+    std::vector<uint32_t> node_words;      // [npad]
+    std::vector<uint32_t> bits;            // [rows][W]
+    std::vector<int32_t> prefix;           // [rows][W]
+    std::vector<SpecialNode> spec;
+    std::vector<BcLink> links;
+    std::vector<int32_t> link_spec, link_dir;  // special index and direction of each link
+    std::vector<int32_t> coords;           // [n][3]
+    bool has_inlet_links = false;
+
+    // parameters
+    bool params_set = false;
+    double tau = 0.0, s[4] = {1, 1, 1, 1}, g[3] = {0, 0, 0};
+    double rho_out = 1.0;
+    bool inlet_set = false;
+    double axis[3] = {0, 0, 1}, center[3] = {0, 0, 0}, radius = 0, G0 = 0, G1 = 0, omega = 0;
+    bool links_dirty = true;
+
+    // device memory
+    char* dev = nullptr;
+    size_t dev_bytes = 0;
+    size_t off_popA = 0, off_popB = 0, off_node = 0, off_bits = 0, off_prefix = 0, off_spec = 0,
+           off_links = 0, off_uspec = 0, off_tcount = 0, off_part = 0, off_monout = 0, off_avg = 0;
+    size_t pop_bytes = 0;
+
+    int cur = 0;
+    int64_t t = 0;
+    int64_t t_upload[2] = {0, 0};
+    bool initialized = false;
+    bool stepped = false;
+    int64_t avg_count = 0;
+    double mon_host[lbm::MON_WORDS] = {0};
+
+    int64_t cell(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
+    int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
+    // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
+    int32_t index_of(int x, int y, int z) const {
+        const int p = x + 1;
+        const size_t r = (size_t)row_of(y, z) * W;
+        const uint32_t wd = bits[r + (p >> 5)];
+        const uint32_t low = (p & 31) ? ((1u << (p & 31)) - 1u) : 0u;
+        return prefix[r + (p >> 5)] + __builtin_popcount(wd & low);
+    }
+};
+
+namespace {
+
+lbm::StepArgs make_args(const lbm_domain* d) {
+    lbm::StepArgs a{};
+    char* base = d->dev;
+    a.fin = base + (d->cur == 0 ? d->off_popA : d->off_popB);
+    a.fout = base + (d->cur == 0 ? d->off_popB : d->off_popA);
+    a.node = (const uint32_t*)(base + d->off_node);
+    a.bits = (const uint32_t*)(base + d->off_bits);
+    a.prefix = (const int32_t*)(base + d->off_prefix);
+    a.spec = (const SpecialNode*)(base + d->off_spec);
+    a.links = (const BcLink*)(base + d->off_links);
+    a.u_spec = (double*)(base + d->off_uspec);
+    a.tcount = (int64_t*)(base + d->off_tcount);
+    a.partials = (double*)(base + d->off_part);
+    a.tin = d->cur;
+    a.n = (int)d->n;
+    a.npad = d->npad;
+    a.nx = d->nx;
+    a.ny = d->ny;
+    a.nz = d->nz;
+    a.W = d->W;
+    a.periodic = (int)d->periodic;
+    a.nblocks = d->nblocks;
+    a.blocks_per_xcd = d->blocks_per_xcd;
+    a.s[0] = 1.0 / d->tau;
+    for (int k = 0; k < 4; ++k) a.s[k + 1] = d->s[k];
+    for (int k = 0; k < 3; ++k) a.g[k] = d->g[k];
+    a.omega = d->omega;
+    const double an = std::sqrt(d->axis[0] * d->axis[0] + d->axis[1] * d->axis[1] + d->axis[2] * d->axis[2]);
+    for (int k = 0; k < 3; ++k) a.axis[k] = an > 0 ? d->axis[k] / an : 0.0;
+    a.rho_out = d->rho_out;
+    return a;
+}
+
+// Recompute the inlet coefficients (they depend on tau through nu) and upload them.
+int prepare_links(lbm_domain* d) {
+    if (!d->links_dirty) return LBM_OK;
+    if (d->links.empty()) {
+        d->links_dirty = false;
+        return LBM_OK;
+    }
+    if (d->has_inlet_links && !d->inlet_set)
+        return fail(LBM_ESTATE, "the mask has inlet cells: call lbm_set_inlet_womersley first");
+    const double nu = (d->tau - 0.5) / 3.0;
+    const double an = std::sqrt(d->axis[0] * d->axis[0] + d->axis[1] * d->axis[1] + d->axis[2] * d->axis[2]);
+    const double ax[3] = {d->axis[0] / an, d->axis[1] / an, d->axis[2] / an};
+    for (size_t k = 0; k < d->links.size(); ++k) {
+        BcLink& L = d->links[k];
+        if (L.type != lbm::LINK_INLET) continue;
+        const SpecialNode& sp = d->spec[d->link_spec[k]];
+        const int a = d->link_dir[k];
+        const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+        // link midpoint between the node and its source x - c_alpha
+        const double m[3] = {sp.x - 0.5 * c[0], sp.y - 0.5 * c[1], sp.z - 0.5 * c[2]};
+        double dv[3], along = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            dv[q] = m[q] - d->center[q];
+            along += dv[q] * ax[q];
+        }
+        double r2 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const double e = dv[q] - along * ax[q];
+            r2 += e * e;
+        }
+        double a0;
+        std::complex<double> a1;
+        womersley_coeffs(std::sqrt(r2), d->radius, nu, d->G0, d->G1, d->omega, &a0, &a1);
+        L.a0 = a0;
+        L.a1re = a1.real();
+        L.a1im = a1.imag();
+    }
+    if (d->dev) {
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_links, d->links.data(), d->links.size() * sizeof(BcLink),
+                               hipMemcpyHostToDevice, d->stream),
+                "upload of boundary links");
+        d->links_dirty = false;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+int lbm_inlet_profile(double r, double t, double radius, double nu, double G0, double G1, double omega,
+                      double* speed) {
+    if (!speed || !(radius > 0) || !(nu > 0) || !std::isfinite(r) || !std::isfinite(t))
+        return fail(LBM_EINVAL, "lbm_inlet_profile: invalid argument");
+    double a0;
+    std::complex<double> a1;
+    womersley_coeffs(r, radius, nu, G0, G1, omega, &a0, &a1);
+    *speed = a0 + a1.real() * std::cos(omega * t) - a1.imag() * std::sin(omega * t);
+    return LBM_OK;
+}
+
+int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                      void* hip_stream, lbm_domain** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mask) return fail(LBM_EINVAL, "mask is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > lbm::MAX_DIM || ny > lbm::MAX_DIM || nz > lbm::MAX_DIM)
+        return fail(LBM_EINVAL, "dimensions must be in [1, 1023]");
+    if (periodic_bits > 7) return fail(LBM_EINVAL, "periodic_bits must be a combination of LBM_PERIODIC_*");
+    if (storage_bytes(storage) == 0) return fail(LBM_EINVAL, "unknown storage type");
+    const int64_t cells = (int64_t)nx * ny * nz;
+    int64_t nfluid = 0;
+    for (int64_t c = 0; c < cells; ++c) {
+        if (mask[c] > LBM_OUTLET) return fail(LBM_EINVAL, "mask values must be 0..3");
+        nfluid += mask[c] == LBM_FLUID;
+    }
+    if (nfluid == 0) return fail(LBM_EINVAL, "the mask has no fluid cell");
+    const int64_t npad = (nfluid + lbm::BLOCK - 1) / lbm::BLOCK * lbm::BLOCK;
+    if (npad * 27 >= ((int64_t)1 << 32)) return fail(LBM_EINVAL, "too many fluid nodes for 32-bit offsets");
+
+    lbm_domain* d = new (std::nothrow) lbm_domain();
+    if (!d) return fail(LBM_ENOMEM, "host allocation failed");
+    try {
+        d->nx = nx;
+        d->ny = ny;
+        d->nz = nz;
+        d->periodic = periodic_bits;
+        d->storage = storage;
+        d->stream = (hipStream_t)hip_stream;
+        d->n = nfluid;
+        d->npad = (int)npad;
+        d->W = ((nx + 1) >> 5) + 2;
+        d->rows = (ny + 2) * (nz + 2);
+        d->nblocks = (int)(npad / lbm::BLOCK);
+        d->blocks_per_xcd = (d->nblocks + 7) / 8;
+
+        // fluid bitmap: bit (x + 1) of row (y, z); one empty row ring around the box
+        d->bits.assign((size_t)d->rows * d->W, 0u);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y) {
+                const size_t r = (size_t)d->row_of(y, z) * d->W;
+                for (int x = 0; x < nx; ++x)
+                    if (mask[d->cell(x, y, z)] == LBM_FLUID) d->bits[r + ((x + 1) >> 5)] |= 1u << ((x + 1) & 31);
+            }
+        d->prefix.assign(d->bits.size(), 0);
+        int64_t cnt = 0;
+        for (size_t k = 0; k < d->bits.size(); ++k) {
+            d->prefix[k] = (int32_t)cnt;
+            cnt += __builtin_popcount(d->bits[k]);
+        }
+        if (cnt != nfluid) return fail(LBM_EINVAL, "internal: bitmap count mismatch");
+
+        d->node_words.assign((size_t)npad, 0u);
+        d->coords.resize((size_t)nfluid * 3);
+        const int dims[3] = {nx, ny, nz};
+        const bool per[3] = {(periodic_bits & 1) != 0, (periodic_bits & 2) != 0, (periodic_bits & 4) != 0};
+        int64_t i = 0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    if (mask[d->cell(x, y, z)] != LBM_FLUID) continue;
+                    d->coords[3 * i] = x;
+                    d->coords[3 * i + 1] = y;
+                    d->coords[3 * i + 2] = z;
+                    // classify the 27 sources x - c_alpha
+                    int kind[27], sx[27], sy[27], sz[27];
+                    bool special = false;
+                    for (int a = 0; a < 27; ++a) {
+                        const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+                        int q[3] = {x - c[0], y - c[1], z - c[2]};
+                        bool inside = true, xwrap = false;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            if (q[ax] < 0 || q[ax] >= dims[ax]) {
+                                if (per[ax]) {
+                                    q[ax] = (q[ax] + dims[ax]) % dims[ax];
+                                    if (ax == 0) xwrap = true;
+                                } else {
+                                    inside = false;
+                                }
+                            }
+                        }
+                        kind[a] = inside ? mask[d->cell(q[0], q[1], q[2])] : LBM_SOLID;
+                        sx[a] = q[0];
+                        sy[a] = q[1];
+                        sz[a] = q[2];
+                        if (kind[a] == LBM_INLET || kind[a] == LBM_OUTLET) special = true;
+                        if (xwrap && kind[a] == LBM_FLUID) special = true;
+                    }
+                    if (d->index_of(x, y, z) != i) return fail(LBM_EINVAL, "internal: index mismatch");
+                    if (!special) {
+                        d->node_words[i] = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+                    } else {
+                        SpecialNode sp{};
+                        sp.node = (int32_t)i;
+                        sp.x = x;
+                        sp.y = y;
+                        sp.z = z;
+                        const int sidx = (int)d->spec.size();
+                        for (int a = 0; a < 27; ++a) {
+                            if (kind[a] == LBM_FLUID) {
+                                sp.src[a] = d->index_of(sx[a], sy[a], sz[a]);
+                            } else if (kind[a] == LBM_SOLID) {
+                                sp.src[a] = lbm::SRC_WALL;
+                            } else {
+                                BcLink L{};
+                                L.type = kind[a] == LBM_INLET ? lbm::LINK_INLET : lbm::LINK_OUTLET;
+                                if (L.type == lbm::LINK_INLET) d->has_inlet_links = true;
+                                sp.src[a] = -2 - (int32_t)d->links.size();
+                                d->links.push_back(L);
+                                d->link_spec.push_back(sidx);
+                                d->link_dir.push_back(a);
+                            }
+                        }
+                        d->spec.push_back(sp);
+                        d->node_words[i] = lbm::SPECIAL_BIT | (uint32_t)sidx;
+                    }
+                    ++i;
+                }
+
+        // device layout
+        const size_t sb = storage_bytes(storage);
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += align256(bytes);
+            return o;
+        };
+        d->pop_bytes = (size_t)27 * npad * sb;
+        d->off_popA = take(d->pop_bytes);
+        d->off_popB = take(d->pop_bytes);
+        d->off_node = take((size_t)npad * 4);
+        d->off_bits = take(d->bits.size() * 4);
+        d->off_prefix = take(d->prefix.size() * 4);
+        d->off_spec = take(std::max<size_t>(1, d->spec.size()) * sizeof(SpecialNode));
+        d->off_links = take(std::max<size_t>(1, d->links.size()) * sizeof(BcLink));
+        d->off_uspec = take(std::max<size_t>(1, d->spec.size()) * 3 * sizeof(double));
+        d->off_tcount = take(2 * sizeof(int64_t));
+        d->off_part = take((size_t)d->nblocks * lbm::MON_WORDS * sizeof(double));
+        d->off_monout = take(lbm::MON_WORDS * sizeof(double));
+        d->off_avg = take((size_t)3 * nfluid * sizeof(double));
+        d->dev_bytes = off;
+    } catch (const std::bad_alloc&) {
+        delete d;
+        return fail(LBM_ENOMEM, "host allocation failed");
+    }
+    *out = d;
+    return LBM_OK;
+}
+
+int lbm_device_bytes(const lbm_domain* d, size_t* bytes) {
+    if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    *bytes = d->dev_bytes;
+    return LBM_OK;
+}
+
+int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
+    if (!d || !dev_ptr) return fail(LBM_EINVAL, "NULL argument");
+    if (bytes < d->dev_bytes) return fail(LBM_ENOMEM, "device buffer smaller than lbm_device_bytes");
+    if (((uintptr_t)dev_ptr & 255u) != 0) return fail(LBM_EINVAL, "device buffer must be 256-byte aligned");
+    d->dev = (char*)dev_ptr;
+    hipStream_t st = d->stream;
+    HIP_TRY(lbm::launch_fill_zero(d->dev, d->dev_bytes, st), "clearing device memory");
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_node, d->node_words.data(), d->node_words.size() * 4,
+                           hipMemcpyHostToDevice, st), "upload of node table");
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_bits, d->bits.data(), d->bits.size() * 4, hipMemcpyHostToDevice, st),
+            "upload of bitmap");
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_prefix, d->prefix.data(), d->prefix.size() * 4,
+                           hipMemcpyHostToDevice, st), "upload of prefix counts");
+    if (!d->spec.empty())
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_spec, d->spec.data(), d->spec.size() * sizeof(SpecialNode),
+                               hipMemcpyHostToDevice, st), "upload of special nodes");
+    d->links_dirty = true;
+    d->initialized = false;
+    d->stepped = false;
+    return LBM_OK;
+}
+
+int lbm_fluid_count(const lbm_domain* d, int64_t* n) {
+    if (!d || !n) return fail(LBM_EINVAL, "NULL argument");
+    *n = d->n;
+    return LBM_OK;
+}
+
+int lbm_fluid_coords(const lbm_domain* d, int32_t* xyz) {
+    if (!d || !xyz) return fail(LBM_EINVAL, "NULL argument");
+    std::memcpy(xyz, d->coords.data(), d->coords.size() * sizeof(int32_t));
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_domain* d, const lbm_params* p) {
+    if (!d || !p) return fail(LBM_EINVAL, "NULL argument");
+    if (p->struct_size != sizeof(lbm_params)) return fail(LBM_EINVAL, "lbm_params.struct_size mismatch");
+    if (!std::isfinite(p->tau) || !(p->tau > 0.5)) return fail(LBM_EINVAL, "tau must be finite and > 1/2");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(p->s[k]) || !(p->s[k] > 0.0) || !(p->s[k] < 2.0))
+            return fail(LBM_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!finite_all(p->g, 3)) return fail(LBM_EINVAL, "body force must be finite");
+    d->tau = p->tau;
+    for (int k = 0; k < 4; ++k) d->s[k] = p->s[k];
+    for (int k = 0; k < 3; ++k) d->g[k] = p->g[k];
+    d->params_set = true;
+    d->links_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_inlet_womersley(lbm_domain* d, const double axis[3], const double center[3], double radius,
+                            double G0, double G1, double omega) {
+    if (!d || !axis || !center) return fail(LBM_EINVAL, "NULL argument");
+    if (!finite_all(axis, 3) || !finite_all(center, 3) || !std::isfinite(radius) || !std::isfinite(G0) ||
+        !std::isfinite(G1) || !std::isfinite(omega))
+        return fail(LBM_EINVAL, "inlet parameters must be finite");
+    if (axis[0] == 0.0 && axis[1] == 0.0 && axis[2] == 0.0) return fail(LBM_EINVAL, "inlet axis is zero");
+    if (!(radius > 0.0)) return fail(LBM_EINVAL, "inlet radius must be > 0");
+    if (omega < 0.0) return fail(LBM_EINVAL, "omega must be >= 0");
+    for (int k = 0; k < 3; ++k) {
+        d->axis[k] = axis[k];
+        d->center[k] = center[k];
+    }
+    d->radius = radius;
+    d->G0 = G0;
+    d->G1 = G1;
+    d->omega = omega;
+    d->inlet_set = true;
+    d->links_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_outlet_pressure(lbm_domain* d, double rho_out) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (!std::isfinite(rho_out) || !(rho_out > 0.0)) return fail(LBM_EINVAL, "rho_out must be finite and > 0");
+    d->rho_out = rho_out;
+    return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
+    if (!d->params_set) return fail(LBM_ESTATE, "call lbm_set_params first");
+    int rc = prepare_links(d);
+    if (rc) return rc;
+    d->cur = 1;   // the init kernel writes into the "next" buffer of slot 1, i.e. buffer A
+    lbm::StepArgs a = make_args(d);
+    a.tin = 0;
+    HIP_TRY(lbm::launch_init(d->storage, a, rho, u, d->stream), "init kernel");
+    d->cur = 0;
+    d->t = 0;
+    d->initialized = true;
+    d->stepped = false;
+    d->avg_count = 0;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_domain* d, int nsteps) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    int rc = prepare_links(d);
+    if (rc) return rc;
+    for (int k = 0; k < nsteps; ++k) {
+        lbm::StepArgs a = make_args(d);
+        HIP_TRY(lbm::launch_step(d->storage, a, k == nsteps - 1, d->stream), "step kernel");
+        d->cur ^= 1;
+        d->t += 1;
+    }
+    if (nsteps > 0) d->stepped = true;
+    return LBM_OK;
+}
+
+int lbm_time(const lbm_domain* d, int64_t* t) {
+    if (!d || !t) return fail(LBM_EINVAL, "NULL argument");
+    *t = d->t;
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_domain* d, double* rho, double* u) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    if (!rho && !u) return LBM_OK;
+    lbm::StepArgs a = make_args(d);
+    HIP_TRY(lbm::launch_moments(d->storage, a, rho, u, nullptr, 0, 0.0, d->stream), "moments kernel");
+    return LBM_OK;
+}
+
+int lbm_average(lbm_domain* d, int op, double* u_avg) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
+    double* acc = (double*)(d->dev + d->off_avg);
+    lbm::StepArgs a = make_args(d);
+    switch (op) {
+        case LBM_AVG_RESET:
+            HIP_TRY(lbm::launch_fill_zero(acc, (size_t)3 * d->n * sizeof(double), d->stream), "average reset");
+            d->avg_count = 0;
+            return LBM_OK;
+        case LBM_AVG_ACCUMULATE:
+            if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+            HIP_TRY(lbm::launch_moments(d->storage, a, nullptr, nullptr, acc, 1, 0.0, d->stream), "average accumulate");
+            d->avg_count += 1;
+            return LBM_OK;
+        case LBM_AVG_READ:
+            if (!u_avg) return fail(LBM_EINVAL, "u_avg is NULL");
+            if (d->avg_count == 0) return fail(LBM_ESTATE, "nothing accumulated");
+            HIP_TRY(lbm::launch_moments(d->storage, a, nullptr, u_avg, acc, 2, (double)d->avg_count, d->stream),
+                    "average read");
+            return LBM_OK;
+        default:
+            return fail(LBM_EINVAL, "unknown average op");
+    }
+}
+
+int lbm_monitors(lbm_domain* d, double out[10]) {
+    if (!d || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->stepped) return fail(LBM_ESTATE, "no step has run since initialisation");
+    double* mo = (double*)(d->dev + d->off_monout);
+    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->nblocks, mo, d->stream),
+            "monitor reduction");
+    HIP_TRY(hipMemcpyAsync(d->mon_host, mo, 9 * sizeof(double), hipMemcpyDeviceToHost, d->stream), "monitor copy");
+    HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");
+    out[0] = (double)d->n + d->mon_host[0];
+    for (int k = 1; k < 9; ++k) out[k] = d->mon_host[k];
+    out[9] = (double)d->t;
+    if (!finite_all(out, 10)) return fail(LBM_EUNSTABLE, "non-finite monitor values: the run diverged");
+    return LBM_OK;
+}
+
+int lbm_read_populations(lbm_domain* d, double* f_dev) {
+    if (!d || !f_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    lbm::StepArgs a = make_args(d);
+    HIP_TRY(lbm::launch_read_populations(d->storage, a, f_dev, d->stream), "population read");
+    return LBM_OK;
+}
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    uint32_t version, storage;
+    int64_t n, nspec, npad, t;
+    uint64_t pop_bytes;
+};
+}  // namespace
+
+int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
+    if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->spec.size() * 3 * sizeof(double);
+    if (!host) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return fail(LBM_EINVAL, "state buffer too small");
+    if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    StateHeader h{};
+    std::memcpy(h.magic, "LBMSTAT1", 8);
+    h.version = 1;
+    h.storage = (uint32_t)d->storage;
+    h.n = d->n;
+    h.nspec = (int64_t)d->spec.size();
+    h.npad = d->npad;
+    h.t = d->t;
+    h.pop_bytes = d->pop_bytes;
+    char* p = (char*)host;
+    std::memcpy(p, &h, sizeof h);
+    const size_t cur_off = d->cur == 0 ? d->off_popA : d->off_popB;
+    HIP_TRY(hipMemcpyAsync(p + sizeof h, d->dev + cur_off, d->pop_bytes, hipMemcpyDeviceToHost, d->stream),
+            "state copy");
+    if (!d->spec.empty())
+        HIP_TRY(hipMemcpyAsync(p + sizeof h + d->pop_bytes, d->dev + d->off_uspec, d->spec.size() * 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, d->stream), "state copy");
+    HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");
+    *bytes = need;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_domain* d, const void* host, size_t bytes) {
+    if (!d || !host) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
+    if (!d->params_set) return fail(LBM_ESTATE, "call lbm_set_params first");
+    StateHeader h;
+    if (bytes < sizeof h) return fail(LBM_EINVAL, "state too short");
+    std::memcpy(&h, host, sizeof h);
+    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->spec.size() * 3 * sizeof(double);
+    if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0 || h.version != 1 || h.storage != (uint32_t)d->storage ||
+        h.n != d->n || h.nspec != (int64_t)d->spec.size() || h.npad != d->npad || h.pop_bytes != d->pop_bytes ||
+        h.t < 0 || bytes < need)
+        return fail(LBM_EINVAL, "state header does not match this domain");
+    int rc = prepare_links(d);
+    if (rc) return rc;
+    const char* p = (const char*)host;
+    d->cur = 0;
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_popA, p + sizeof h, d->pop_bytes, hipMemcpyHostToDevice, d->stream),
+            "state upload");
+    if (!d->spec.empty())
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_uspec, p + sizeof h + d->pop_bytes, d->spec.size() * 3 * sizeof(double),
+                               hipMemcpyHostToDevice, d->stream), "state upload");
+    d->t_upload[0] = h.t;
+    d->t_upload[1] = h.t;
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_tcount, d->t_upload, sizeof d->t_upload, hipMemcpyHostToDevice, d->stream),
+            "state upload");
+    HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");
+    d->t = h.t;
+    d->initialized = true;
+    d->stepped = false;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_domain* d) { delete d; }
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Thin Python binding of ``liblbm.so`` (C ABI declared in include/lbm.h).
+
+The functions below carry the same names and arguments as the C entry points
+and only marshal arguments; every step of the lattice Boltzmann path runs in
+the library's HIP kernels.  PyTorch is used for device memory and the stream.
+If the library is missing the import fails loudly: there is no other
+implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
+LBM_SOLID, LBM_FLUID, LBM_INLET, LBM_OUTLET = 0, 1, 2, 3
+LBM_PERIODIC_X, LBM_PERIODIC_Y, LBM_PERIODIC_Z = 1, 2, 4
+LBM_AVG_RESET, LBM_AVG_ACCUMULATE, LBM_AVG_READ = 0, 1, 2
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
+STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
+
+EXPORTED = [
+    "lbm_last_error", "lbm_create_domain", "lbm_device_bytes", "lbm_attach_device",
+    "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_inlet_womersley",
+    "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
+    "lbm_average", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
+    "lbm_inlet_profile", "lbm_destroy",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("tau", ctypes.c_double),
+                ("s", ctypes.c_double * 4), ("g", ctypes.c_double * 3)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2101_11107_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "lbm_last_error": ([], ctypes.c_char_p),
+        "lbm_create_domain": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int, _P,
+                               ctypes.POINTER(_P)], ctypes.c_int),
+        "lbm_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
+        "lbm_fluid_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lbm_fluid_coords": ([_P, _P], ctypes.c_int),
+        "lbm_set_params": ([_P, ctypes.POINTER(lbm_params)], ctypes.c_int),
+        "lbm_set_inlet_womersley": ([_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double], ctypes.c_int),
+        "lbm_set_outlet_pressure": ([_P, ctypes.c_double], ctypes.c_int),
+        "lbm_init_equilibrium": ([_P, _P, _P], ctypes.c_int),
+        "lbm_step": ([_P, ctypes.c_int], ctypes.c_int),
+        "lbm_time": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lbm_moments": ([_P, _P, _P], ctypes.c_int),
+        "lbm_average": ([_P, ctypes.c_int, _P], ctypes.c_int),
+        "lbm_monitors": ([_P, _P], ctypes.c_int),
+        "lbm_read_populations": ([_P, _P], ctypes.c_int),
+        "lbm_get_state": ([_P, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_set_state": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
+        "lbm_inlet_profile": ([ctypes.c_double] * 7 + [ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "lbm_destroy": ([_P], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error().decode())
+    return rc
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor, or NULL for None."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---- one function per C entry point (argument marshalling only) ----------------------
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode()
+
+
+def lbm_create_domain(mask: np.ndarray, periodic_bits: int, storage: int, hip_stream: int):
+    """mask: uint8 [nz, ny, nx]; returns the opaque domain handle."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = m.shape
+    out = _P()
+    _check(load().lbm_create_domain(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), int(storage),
+                                    _P(hip_stream), ctypes.byref(out)))
+    return out
+
+
+def lbm_device_bytes(dom) -> int:
+    v = ctypes.c_size_t()
+    _check(load().lbm_device_bytes(dom, ctypes.byref(v)))
+    return v.value
+
+
+def lbm_attach_device(dom, dev_tensor) -> None:
+    _check(load().lbm_attach_device(dom, _dptr(dev_tensor), dev_tensor.numel() * dev_tensor.element_size()))
+
+
+def lbm_fluid_count(dom) -> int:
+    v = ctypes.c_int64()
+    _check(load().lbm_fluid_count(dom, ctypes.byref(v)))
+    return v.value
+
+
+def lbm_fluid_coords(dom) -> np.ndarray:
+    n = lbm_fluid_count(dom)
+    out = np.empty((n, 3), np.int32)
+    _check(load().lbm_fluid_coords(dom, out.ctypes.data_as(_P)))
+    return out
+
+
+def lbm_set_params(dom, tau: float, s=(1.0, 1.0, 1.0, 1.0), g=(0.0, 0.0, 0.0)) -> None:
+    p = lbm_params()
+    p.struct_size = ctypes.sizeof(lbm_params)
+    p.tau = float(tau)
+    for k in range(4):
+        p.s[k] = float(s[k])
+    for k in range(3):
+        p.g[k] = float(g[k])
+    _check(load().lbm_set_params(dom, ctypes.byref(p)))
+
+
+def lbm_set_inlet_womersley(dom, axis, center, radius, G0, G1, omega) -> None:
+    ax = (ctypes.c_double * 3)(*[float(v) for v in axis])
+    ce = (ctypes.c_double * 3)(*[float(v) for v in center])
+    _check(load().lbm_set_inlet_womersley(dom, ax, ce, float(radius), float(G0), float(G1), float(omega)))
+
+
+def lbm_set_outlet_pressure(dom, rho_out: float) -> None:
+    _check(load().lbm_set_outlet_pressure(dom, float(rho_out)))
+
+
+def lbm_init_equilibrium(dom, rho=None, u=None) -> None:
+    _check(load().lbm_init_equilibrium(dom, _dptr(rho), _dptr(u)))
+
+
+def lbm_step(dom, nsteps: int) -> None:
+    _check(load().lbm_step(dom, int(nsteps)))
+
+
+def lbm_time(dom) -> int:
+    v = ctypes.c_int64()
+    _check(load().lbm_time(dom, ctypes.byref(v)))
+    return v.value
+
+
+def lbm_moments(dom, rho=None, u=None) -> None:
+    _check(load().lbm_moments(dom, _dptr(rho), _dptr(u)))
+
+
+def lbm_average(dom, op: int, u_avg=None) -> None:
+    _check(load().lbm_average(dom, int(op), _dptr(u_avg)))
+
+
+def lbm_monitors(dom) -> np.ndarray:
+    out = np.zeros(10, np.float64)
+    _check(load().lbm_monitors(dom, out.ctypes.data_as(_P)))
+    return out
+
+
+def lbm_read_populations(dom, f_dev) -> None:
+    _check(load().lbm_read_populations(dom, _dptr(f_dev)))
+
+
+def lbm_get_state(dom) -> bytes:
+    n = ctypes.c_size_t()
+    _check(load().lbm_get_state(dom, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(load().lbm_get_state(dom, buf, ctypes.byref(n)))
+    return buf.raw[: n.value]
+
+
+def lbm_set_state(dom, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(load().lbm_set_state(dom, buf, len(blob)))
+
+
+def lbm_inlet_profile(r, t, radius, nu, G0, G1, omega) -> float:
+    v = ctypes.c_double()
+    _check(load().lbm_inlet_profile(float(r), float(t), float(radius), float(nu), float(G0), float(G1),
+                                    float(omega), ctypes.byref(v)))
+    return v.value
+
+
+def lbm_destroy(dom) -> None:
+    if dom:
+        load().lbm_destroy(dom)
+
+
+# ---- convenience owner of a domain and its device memory ------------------------------
+
+class Domain:
+    """A domain plus the torch tensor that holds its device memory.
+
+    ``case`` is any object with ``mask``, ``periodic``, ``tau``, ``rates``,
+    ``g``, ``rho_out`` and ``inlet`` attributes (see the ``synth`` package).
+    """
+
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required (the library has no CPU path)")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.case = case
+        self.handle = lbm_create_domain(case.mask, case.periodic, self.storage, self.stream.cuda_stream)
+        self.n = lbm_fluid_count(self.handle)
+        nbytes = lbm_device_bytes(self.handle)
+        self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.mem.data_ptr()) % 256
+        self.view = self.mem[off: off + nbytes]
+        lbm_attach_device(self.handle, self.view)
+        lbm_set_params(self.handle, case.tau, case.rates, case.g)
+        if case.inlet is not None:
+            i = case.inlet
+            lbm_set_inlet_womersley(self.handle, i.axis, i.center, i.radius, i.G0, i.G1, i.omega)
+        lbm_set_outlet_pressure(self.handle, case.rho_out)
+
+    def init(self, rho=None, u=None):
+        lbm_init_equilibrium(self.handle, rho, u)
+
+    def step(self, n):
+        lbm_step(self.handle, n)
+
+    def coords(self):
+        return lbm_fluid_coords(self.handle)
+
+    def moments(self):
+        t = self.torch
+        rho = t.empty(self.n, dtype=t.float64, device=self.device)
+        u = t.empty((3, self.n), dtype=t.float64, device=self.device)
+        lbm_moments(self.handle, rho, u)
+        return rho, u
+
+    def populations(self):
+        t = self.torch
+        f = t.empty((27, self.n), dtype=t.float64, device=self.device)
+        lbm_read_populations(self.handle, f)
+        return f
+
+    def monitors(self):
+        return lbm_monitors(self.handle)
+
+    def time(self):
+        return lbm_time(self.handle)
+
+    def close(self):
+        if self.handle:
+            self.stream.synchronize()
+            lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

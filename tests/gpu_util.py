@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU tests: run the library and the oracle on one case."""
+
+import numpy as np
+
+W = np.array([(1 / 6 if cx else 2 / 3) * (1 / 6 if cy else 2 / 3) * (1 / 6 if cz else 2 / 3)
+              for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)], np.float64)
+
+
+def gpu_run(case, storage, steps, device="cuda:0"):
+    """Run the HIP path; return (domain, shifted post-collision populations [n, 27] as FP64)."""
+    import torch
+    from paper_2101_11107_amd import lbm
+    dom = lbm.Domain(case, storage=storage, device=device)
+    dom.init()
+    if steps:
+        dom.step(steps)
+    f = dom.populations().cpu().numpy().T.copy()
+    torch.cuda.synchronize()
+    return dom, f
+
+
+def oracle_post(case, steps, nthreads=16):
+    """Oracle tier O2: shifted post-collision populations f*(steps) - w and u(steps)."""
+    from oracle import o2
+    sim = o2.O2Sim(case, nthreads=nthreads)
+    if steps:
+        sim.run(steps)
+    rho, u = sim.macroscopic()
+    sim.collide()
+    return sim, sim.fpost - W[None, :], rho, u
+
+
+def moments_from_post(fhat, g):
+    """rho, u of the pre-collision state from shifted post-collision populations."""
+    rho = 1.0 + fhat.sum(axis=1)
+    j = fhat @ C
+    u = (j - 0.5 * rho[:, None] * np.asarray(g, np.float64)[None, :]) / rho[:, None]
+    return rho, u
+
+
+def eps_u(u_gpu, u_ref):
+    return float(np.max(np.abs(u_gpu - u_ref)) / np.max(np.abs(u_ref)))
