@@ -1,0 +1,204 @@
+"""Benchmark of the D3Q27 CHM-MRT step on one MI355X.
+
+Default workload: the 256^3 synthetic aneurysm (seed 0, Womersley inlet with
+alpha = 3 and a 4000-step period, zero-pressure outlet, tau = 0.5754), shifted
+populations stored in FP32.  A step is one fused stream-collide launch over
+every fluid node (with its monitor partials); K steps are timed with HIP events
+on the library's stream after W warm-up steps, inputs resident in HBM.
+
+Prints one JSON line: fluid-node MLUPS, the roofline of the step kernel
+(algorithmic bytes 54 populations x storage bytes per node update), the FP64
+CPU oracle timed on a bounded sample on the host cores, and (``also``) the
+other storage forms and the 512^3 geometry with their velocity error against
+the FP64 run of the same geometry.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, 8 TB/s
+POP_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+STEP_KERNEL = "k_step"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(storage, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{STEP_KERNEL}_{storage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_form(torch, lbm, case, storage, warmup, steps, want_u=False):
+    dom = lbm.Domain(case, storage=storage, device="cuda:0")
+    dom.init()
+    dom.step(warmup)
+    dom.stream.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(dom.stream)
+    dom.step(steps)
+    ev1.record(dom.stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    mon = dom.monitors()
+    out = dict(n=dom.n, ms=ms, ms_per_step=ms / steps, mlups=dom.n * steps / (ms * 1e-3) / 1e6,
+               monitors=mon)
+    if want_u:
+        _, u = dom.moments()
+        out["u"] = u.cpu().numpy()
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(n, ms_per_step, storage, traffic):
+    alg = 54 * POP_BYTES[storage] * n                 # algorithmic bytes per launch
+    achieved = alg / (ms_per_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg}
+
+
+def cpu_baseline(case, budget_s):
+    """Oracle tier O2 (FP64, OpenMP) on the same case, bounded to ~budget_s."""
+    from oracle import o2
+    o2.build(force=False)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sim = o2.O2Sim(case, nthreads=threads)
+    sim.run(2)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s:
+        sim.run(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": round(sim.n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{case.name}: {steps} steps of the FP64 C/OpenMP oracle from rest "
+                      f"({sim.n} fluid nodes, {dt:.1f} s)"}
+
+
+def rel_l2(u, ref):
+    import numpy as np
+    return float(np.sqrt(((u - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="f32", choices=list(POP_BYTES))
+    ap.add_argument("--workload", default="aneurysm256", choices=["aneurysm256", "aneurysm512"],
+                    help="geometry of the timed run (profiling runs use the 512^3 one)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other storage forms and sizes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the method's multi-GPU "
+              "decomposition is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2101_11107_amd import lbm
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    workload = args.workload
+    size = 256 if workload == "aneurysm256" else 512
+    case = synth.aneurysm_case(size, seed=0)
+    main_run = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=not args.no_extra)
+    traffic = read_traffic(args.storage, workload)
+    line = {
+        "metric": "fluid-node MLUPS (D3Q27 CHM-MRT fused stream-collide step)",
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"{workload}_seed0_womersley_alpha3_period{case.period}", "box": [size] * 3,
+                   "fluid_nodes": main_run["n"], "storage": args.storage, "tau": round(case.tau, 6),
+                   "steps_per_graph": 16},
+        "roofline": roofline(main_run["n"], main_run["ms_per_step"], args.storage, traffic),
+    }
+    mon = main_run["monitors"]
+    line["monitors_last_step"] = {"mass": mon[0], "inlet_flux": mon[7], "outlet_flux": mon[8], "t": mon[9]}
+
+    if not args.no_extra:
+        also = []
+        steps_x = 1000
+        ref = run_form(torch, lbm, case, "f64", args.warmup, args.steps, want_u=True)
+        also.append({"workload": workload, "storage": "f64", "mlups": round(ref["mlups"], 1),
+                     "roofline_frac": roofline(ref["n"], ref["ms_per_step"], "f64", None)["frac"]})
+        line["f32_velocity_rel_l2_vs_f64"] = rel_l2(main_run["u"], ref["u"])
+        for st in ("f16s", "bf16s"):
+            r = run_form(torch, lbm, case, st, args.warmup, args.steps, want_u=True)
+            also.append({"workload": workload, "storage": st, "mlups": round(r["mlups"], 1),
+                         "roofline_frac": roofline(r["n"], r["ms_per_step"], st, None)["frac"],
+                         "u_rel_l2_vs_f64": rel_l2(r["u"], ref["u"]),
+                         "mass_drift_vs_f64": abs(r["monitors"][0] - ref["monitors"][0]) / ref["monitors"][0]})
+        big = synth.aneurysm_case(512, seed=0)
+        for st in ("f32", "f16s", "bf16s", "f64"):
+            r = run_form(torch, lbm, big, st, 100, steps_x)
+            rf = roofline(r["n"], r["ms_per_step"], st, read_traffic(st, "aneurysm512"))
+            also.append({"workload": "aneurysm512", "storage": st, "fluid_nodes": r["n"],
+                         "mlups": round(r["mlups"], 1), "achieved_GBs": rf["achieved"],
+                         "roofline_frac": rf["frac"], "traffic": rf["traffic"], "steps": steps_x})
+        line["also"] = also
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

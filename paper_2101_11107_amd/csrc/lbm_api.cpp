@@ -14,7 +14,6 @@
 #include "lbm.h"
 #include "lbm_internal.h"
 
-using lbm::BcLink;
 using lbm::SpecialNode;
 
 namespace {
@@ -97,13 +96,15 @@ struct lbm_domain {
     int rows = 0;
     int nblocks = 0, blocks_per_xcd = 0;
     std::vector<uint32_t> node_words;      // [npad]
-    std::vector<uint32_t> bits;            // [rows][W]
-    std::vector<int32_t> prefix;           // [rows][W]
+    std::vector<lbm::RowEntry> rowtab;     // [rows][W]
     std::vector<SpecialNode> spec;
-    std::vector<BcLink> links;
-    std::vector<int32_t> link_spec, link_dir;  // special index and direction of each link
+    std::vector<int32_t> spec_plane;       // [nspec][27] plane of each pulled value
+    std::vector<int32_t> link_meta;        // [nlinks] type | alpha << 8
+    std::vector<double> link_coef;         // [nlinks][LINK_COEFS]
+    std::vector<int32_t> link_xyz;         // [nlinks][3] node coordinates of each link
     std::vector<int32_t> coords;           // [n][3]
     bool has_inlet_links = false;
+    size_t nlinks() const { return link_meta.size(); }
 
     // parameters
     bool params_set = false;
@@ -116,28 +117,42 @@ struct lbm_domain {
     // device memory
     char* dev = nullptr;
     size_t dev_bytes = 0;
-    size_t off_popA = 0, off_popB = 0, off_node = 0, off_bits = 0, off_prefix = 0, off_spec = 0,
-           off_links = 0, off_uspec = 0, off_tcount = 0, off_part = 0, off_monout = 0, off_avg = 0;
+    size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
+           off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0;
     size_t pop_bytes = 0;
 
     int cur = 0;
     int64_t t = 0;
     int64_t t_upload[2] = {0, 0};
+    double trig_host[4] = {1, 0, 1, 0};   // (cos, sin)(omega t) for slots t & 1
     bool initialized = false;
-    bool stepped = false;
+    bool monitored = false;   // a monitored step ran since initialisation
     int64_t avg_count = 0;
     double mon_host[lbm::MON_WORDS] = {0};
+
+    // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer
+    // parity.  Kernel arguments are baked in, so any parameter change drops them.
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+    void drop_graphs() {
+        for (auto& g : graph) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
+    ~lbm_domain() { drop_graphs(); }
 
     int64_t cell(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
     int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
     // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
     int32_t index_of(int x, int y, int z) const {
         const int p = x + 1;
-        const size_t r = (size_t)row_of(y, z) * W;
-        const uint32_t wd = bits[r + (p >> 5)];
+        const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + (p >> 5)];
         const uint32_t low = (p & 31) ? ((1u << (p & 31)) - 1u) : 0u;
-        return prefix[r + (p >> 5)] + __builtin_popcount(wd & low);
+        return e.prefix + __builtin_popcount(e.bits & low);
     }
+    bool rates_one() const { return s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0; }
+    bool periodic_yz() const { return (periodic & 6u) != 0; }
 };
 
 namespace {
@@ -148,12 +163,15 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.fin = base + (d->cur == 0 ? d->off_popA : d->off_popB);
     a.fout = base + (d->cur == 0 ? d->off_popB : d->off_popA);
     a.node = (const uint32_t*)(base + d->off_node);
-    a.bits = (const uint32_t*)(base + d->off_bits);
-    a.prefix = (const int32_t*)(base + d->off_prefix);
+    a.rowtab = (const lbm::RowEntry*)(base + d->off_rowtab);
     a.spec = (const SpecialNode*)(base + d->off_spec);
-    a.links = (const BcLink*)(base + d->off_links);
-    a.u_spec = (double*)(base + d->off_uspec);
+    a.link_meta = (const int32_t*)(base + d->off_lmeta);
+    a.link_coef = (const double*)(base + d->off_lcoef);
+    a.link_add = (double*)(base + d->off_ladd);
     a.tcount = (int64_t*)(base + d->off_tcount);
+    a.trig = (double*)(base + d->off_trig);
+    a.cos_w = std::cos(d->omega);
+    a.sin_w = std::sin(d->omega);
     a.partials = (double*)(base + d->off_part);
     a.tin = d->cur;
     a.n = (int)d->n;
@@ -175,10 +193,49 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     return a;
 }
 
-// Recompute the inlet coefficients (they depend on tau through nu) and upload them.
+// Exact odd polynomial of the moving-wall term f_eq_a(1, axis U) - f_eq_abar(1, axis U)
+// in the speed U: the product form of the equilibrium is prod_d psi(c_d, axis_d U)
+// with psi(0, v) = 2/3 - v^2 and psi(+-1, v) = (1/3 + v^2 +- v)/2; reversing c
+// flips the odd coefficients, so the difference is twice the odd part.
+void moving_wall_poly(int a, const double ax[3], double k[3]) {
+    const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+    double P[7] = {1, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        const double p0 = c[d] == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+        const double p1 = c[d] == 0 ? 0.0 : 0.5 * c[d] * ax[d];
+        const double p2 = c[d] == 0 ? -ax[d] * ax[d] : 0.5 * ax[d] * ax[d];
+        double Q[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < 5; ++i) {
+            Q[i] += P[i] * p0;
+            Q[i + 1] += P[i] * p1;
+            Q[i + 2] += P[i] * p2;
+        }
+        std::memcpy(P, Q, sizeof P);
+    }
+    k[0] = 2.0 * P[1];
+    k[1] = 2.0 * P[3];
+    k[2] = 2.0 * P[5];
+}
+
+// Inlet phase slots for time t: slot t & 1 holds (cos, sin)(omega t), slot
+// (t + 1) & 1 the next time.
+int upload_phase(lbm_domain* d, int64_t t) {
+    for (int q = 0; q < 2; ++q) {
+        const int64_t tt = t + q;
+        const double ph = d->omega * (double)tt;
+        d->trig_host[2 * (tt & 1)] = std::cos(ph);
+        d->trig_host[2 * (tt & 1) + 1] = std::sin(ph);
+    }
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_trig, d->trig_host, sizeof d->trig_host, hipMemcpyHostToDevice, d->stream),
+            "upload of the inlet phase");
+    return LBM_OK;
+}
+
+// Recompute the inlet coefficients (they depend on tau through nu) and upload
+// them with the inlet phase of the current time.
 int prepare_links(lbm_domain* d) {
     if (!d->links_dirty) return LBM_OK;
-    if (d->links.empty()) {
+    if (d->nlinks() == 0) {
         d->links_dirty = false;
         return LBM_OK;
     }
@@ -187,14 +244,15 @@ int prepare_links(lbm_domain* d) {
     const double nu = (d->tau - 0.5) / 3.0;
     const double an = std::sqrt(d->axis[0] * d->axis[0] + d->axis[1] * d->axis[1] + d->axis[2] * d->axis[2]);
     const double ax[3] = {d->axis[0] / an, d->axis[1] / an, d->axis[2] / an};
-    for (size_t k = 0; k < d->links.size(); ++k) {
-        BcLink& L = d->links[k];
-        if (L.type != lbm::LINK_INLET) continue;
-        const SpecialNode& sp = d->spec[d->link_spec[k]];
-        const int a = d->link_dir[k];
+    for (size_t k = 0; k < d->nlinks(); ++k) {
+        double* cf = &d->link_coef[lbm::LINK_COEFS * k];
+        for (int q = 0; q < lbm::LINK_COEFS; ++q) cf[q] = 0.0;
+        if ((d->link_meta[k] & 0xff) != lbm::LINK_INLET) continue;
+        const int a = d->link_meta[k] >> 8;
         const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+        const int32_t* p = &d->link_xyz[3 * k];
         // link midpoint between the node and its source x - c_alpha
-        const double m[3] = {sp.x - 0.5 * c[0], sp.y - 0.5 * c[1], sp.z - 0.5 * c[2]};
+        const double m[3] = {p[0] - 0.5 * c[0], p[1] - 0.5 * c[1], p[2] - 0.5 * c[2]};
         double dv[3], along = 0.0;
         for (int q = 0; q < 3; ++q) {
             dv[q] = m[q] - d->center[q];
@@ -208,16 +266,53 @@ int prepare_links(lbm_domain* d) {
         double a0;
         std::complex<double> a1;
         womersley_coeffs(std::sqrt(r2), d->radius, nu, d->G0, d->G1, d->omega, &a0, &a1);
-        L.a0 = a0;
-        L.a1re = a1.real();
-        L.a1im = a1.imag();
+        cf[0] = a0;
+        cf[1] = a1.real();
+        cf[2] = a1.imag();
+        moving_wall_poly(a, ax, cf + 3);
     }
     if (d->dev) {
-        HIP_TRY(hipMemcpyAsync(d->dev + d->off_links, d->links.data(), d->links.size() * sizeof(BcLink),
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_lcoef, d->link_coef.data(), d->link_coef.size() * sizeof(double),
                                hipMemcpyHostToDevice, d->stream),
                 "upload of boundary links");
+        int rc = upload_phase(d, d->t);
+        if (rc) return rc;
         d->links_dirty = false;
     }
+    return LBM_OK;
+}
+
+constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffer parity
+
+// Launch nsteps steps; the last one accumulates the monitors.
+int launch_steps_eager(lbm_domain* d, int nsteps) {
+    for (int k = 0; k < nsteps; ++k) {
+        lbm::StepArgs a = make_args(d);
+        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz()};
+        HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
+        d->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+// Capture GRAPH_STEPS steps starting from the current parity into a graph.
+int build_graph(lbm_domain* d) {
+    const int par = d->cur;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(d->stream, hipStreamCaptureModeRelaxed), "graph capture begin");
+    int rc = launch_steps_eager(d, GRAPH_STEPS);
+    hipError_t e = hipStreamEndCapture(d->stream, &g);
+    d->cur = par;   // nothing ran during capture
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture end");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    d->graph[par] = ex;
     return LBM_OK;
 }
 
@@ -255,7 +350,8 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
     }
     if (nfluid == 0) return fail(LBM_EINVAL, "the mask has no fluid cell");
     const int64_t npad = (nfluid + lbm::BLOCK - 1) / lbm::BLOCK * lbm::BLOCK;
-    if (npad * 27 >= ((int64_t)1 << 32)) return fail(LBM_EINVAL, "too many fluid nodes for 32-bit offsets");
+    if (npad * 27 * (int64_t)storage_bytes(storage) >= ((int64_t)1 << 32))
+        return fail(LBM_EINVAL, "too many fluid nodes for 32-bit byte offsets");
 
     lbm_domain* d = new (std::nothrow) lbm_domain();
     if (!d) return fail(LBM_ENOMEM, "host allocation failed");
@@ -273,26 +369,28 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
         d->nblocks = (int)(npad / lbm::BLOCK);
         d->blocks_per_xcd = (d->nblocks + 7) / 8;
 
-        // fluid bitmap: bit (x + 1) of row (y, z); one empty row ring around the box
-        d->bits.assign((size_t)d->rows * d->W, 0u);
+        // row table: fluid bitmap (bit x + 1 of row (y, z), one empty row ring
+        // around the box) and the count of fluid nodes before each word
+        d->rowtab.assign((size_t)d->rows * d->W, lbm::RowEntry{0u, 0});
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y) {
                 const size_t r = (size_t)d->row_of(y, z) * d->W;
                 for (int x = 0; x < nx; ++x)
-                    if (mask[d->cell(x, y, z)] == LBM_FLUID) d->bits[r + ((x + 1) >> 5)] |= 1u << ((x + 1) & 31);
+                    if (mask[d->cell(x, y, z)] == LBM_FLUID) d->rowtab[r + ((x + 1) >> 5)].bits |= 1u << ((x + 1) & 31);
             }
-        d->prefix.assign(d->bits.size(), 0);
         int64_t cnt = 0;
-        for (size_t k = 0; k < d->bits.size(); ++k) {
-            d->prefix[k] = (int32_t)cnt;
-            cnt += __builtin_popcount(d->bits[k]);
+        for (auto& e : d->rowtab) {
+            e.prefix = (int32_t)cnt;
+            cnt += __builtin_popcount(e.bits);
         }
         if (cnt != nfluid) return fail(LBM_EINVAL, "internal: bitmap count mismatch");
+        if ((int64_t)d->rows * d->W >= ((int64_t)1 << 29)) return fail(LBM_EINVAL, "box too large for the row table");
 
         d->node_words.assign((size_t)npad, 0u);
         d->coords.resize((size_t)nfluid * 3);
         const int dims[3] = {nx, ny, nz};
         const bool per[3] = {(periodic_bits & 1) != 0, (periodic_bits & 2) != 0, (periodic_bits & 4) != 0};
+        const bool per_yz = per[1] || per[2];
         int64_t i = 0;
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
@@ -327,27 +425,34 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                     }
                     if (d->index_of(x, y, z) != i) return fail(LBM_EINVAL, "internal: index mismatch");
                     if (!special) {
-                        d->node_words[i] = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+                        d->node_words[i] = per_yz ? ((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20))
+                                                  : ((uint32_t)x | ((uint32_t)d->row_of(y, z) << 10));
                     } else {
                         SpecialNode sp{};
                         sp.node = (int32_t)i;
-                        sp.x = x;
-                        sp.y = y;
-                        sp.z = z;
+                        sp.link0 = (int32_t)d->nlinks();
                         const int sidx = (int)d->spec.size();
                         for (int a = 0; a < 27; ++a) {
+                            // element index and plane of the pulled value; turned into
+                            // byte offsets once the storage size is applied below
                             if (kind[a] == LBM_FLUID) {
-                                sp.src[a] = d->index_of(sx[a], sy[a], sz[a]);
-                            } else if (kind[a] == LBM_SOLID) {
-                                sp.src[a] = lbm::SRC_WALL;
+                                sp.off[a] = (uint32_t)d->index_of(sx[a], sy[a], sz[a]);
+                                d->spec_plane.push_back(a);
                             } else {
-                                BcLink L{};
-                                L.type = kind[a] == LBM_INLET ? lbm::LINK_INLET : lbm::LINK_OUTLET;
-                                if (L.type == lbm::LINK_INLET) d->has_inlet_links = true;
-                                sp.src[a] = -2 - (int32_t)d->links.size();
-                                d->links.push_back(L);
-                                d->link_spec.push_back(sidx);
-                                d->link_dir.push_back(a);
+                                sp.off[a] = (uint32_t)i;
+                                d->spec_plane.push_back(26 - a);
+                                if (kind[a] == LBM_SOLID) {
+                                    sp.wallmask |= 1u << a;
+                                } else {
+                                    const int32_t type = kind[a] == LBM_INLET ? lbm::LINK_INLET : lbm::LINK_OUTLET;
+                                    if (type == lbm::LINK_INLET) d->has_inlet_links = true;
+                                    sp.linkmask |= 1u << a;
+                                    d->link_meta.push_back(type | (a << 8));
+                                    d->link_xyz.push_back(x);
+                                    d->link_xyz.push_back(y);
+                                    d->link_xyz.push_back(z);
+                                    for (int q = 0; q < lbm::LINK_COEFS; ++q) d->link_coef.push_back(0.0);
+                                }
                             }
                         }
                         d->spec.push_back(sp);
@@ -365,15 +470,24 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
             return o;
         };
         d->pop_bytes = (size_t)27 * npad * sb;
+        for (size_t k = 0; k < d->spec.size(); ++k)
+            for (int a = 0; a < 27; ++a) {
+                const uint64_t byte = ((uint64_t)d->spec_plane[27 * k + a] * (uint64_t)npad + d->spec[k].off[a]) * sb;
+                d->spec[k].off[a] = (uint32_t)byte;
+            }
+        d->spec_plane.clear();
+        d->spec_plane.shrink_to_fit();
         d->off_popA = take(d->pop_bytes);
         d->off_popB = take(d->pop_bytes);
         d->off_node = take((size_t)npad * 4);
-        d->off_bits = take(d->bits.size() * 4);
-        d->off_prefix = take(d->prefix.size() * 4);
+        d->off_rowtab = take(d->rowtab.size() * sizeof(lbm::RowEntry) + 16);
         d->off_spec = take(std::max<size_t>(1, d->spec.size()) * sizeof(SpecialNode));
-        d->off_links = take(std::max<size_t>(1, d->links.size()) * sizeof(BcLink));
-        d->off_uspec = take(std::max<size_t>(1, d->spec.size()) * 3 * sizeof(double));
+        const size_t nl = std::max<size_t>(1, d->nlinks());
+        d->off_lmeta = take(nl * sizeof(int32_t));
+        d->off_lcoef = take(nl * lbm::LINK_COEFS * sizeof(double));
+        d->off_ladd = take(nl * sizeof(double));
         d->off_tcount = take(2 * sizeof(int64_t));
+        d->off_trig = take(4 * sizeof(double));
         d->off_part = take((size_t)d->nblocks * lbm::MON_WORDS * sizeof(double));
         d->off_monout = take(lbm::MON_WORDS * sizeof(double));
         d->off_avg = take((size_t)3 * nfluid * sizeof(double));
@@ -397,20 +511,22 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     if (bytes < d->dev_bytes) return fail(LBM_ENOMEM, "device buffer smaller than lbm_device_bytes");
     if (((uintptr_t)dev_ptr & 255u) != 0) return fail(LBM_EINVAL, "device buffer must be 256-byte aligned");
     d->dev = (char*)dev_ptr;
+    d->drop_graphs();
     hipStream_t st = d->stream;
     HIP_TRY(lbm::launch_fill_zero(d->dev, d->dev_bytes, st), "clearing device memory");
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_node, d->node_words.data(), d->node_words.size() * 4,
                            hipMemcpyHostToDevice, st), "upload of node table");
-    HIP_TRY(hipMemcpyAsync(d->dev + d->off_bits, d->bits.data(), d->bits.size() * 4, hipMemcpyHostToDevice, st),
-            "upload of bitmap");
-    HIP_TRY(hipMemcpyAsync(d->dev + d->off_prefix, d->prefix.data(), d->prefix.size() * 4,
-                           hipMemcpyHostToDevice, st), "upload of prefix counts");
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_rowtab, d->rowtab.data(), d->rowtab.size() * sizeof(lbm::RowEntry),
+                           hipMemcpyHostToDevice, st), "upload of row table");
     if (!d->spec.empty())
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_spec, d->spec.data(), d->spec.size() * sizeof(SpecialNode),
                                hipMemcpyHostToDevice, st), "upload of special nodes");
+    if (d->nlinks())
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_lmeta, d->link_meta.data(), d->nlinks() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st), "upload of link table");
     d->links_dirty = true;
     d->initialized = false;
-    d->stepped = false;
+    d->monitored = false;
     return LBM_OK;
 }
 
@@ -439,6 +555,7 @@ int lbm_set_params(lbm_domain* d, const lbm_params* p) {
     for (int k = 0; k < 3; ++k) d->g[k] = p->g[k];
     d->params_set = true;
     d->links_dirty = true;
+    d->drop_graphs();
     return LBM_OK;
 }
 
@@ -461,6 +578,7 @@ int lbm_set_inlet_womersley(lbm_domain* d, const double axis[3], const double ce
     d->omega = omega;
     d->inlet_set = true;
     d->links_dirty = true;
+    d->drop_graphs();
     return LBM_OK;
 }
 
@@ -468,6 +586,7 @@ int lbm_set_outlet_pressure(lbm_domain* d, double rho_out) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (!std::isfinite(rho_out) || !(rho_out > 0.0)) return fail(LBM_EINVAL, "rho_out must be finite and > 0");
     d->rho_out = rho_out;
+    d->drop_graphs();
     return LBM_OK;
 }
 
@@ -475,7 +594,10 @@ int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
     if (!d->params_set) return fail(LBM_ESTATE, "call lbm_set_params first");
+    d->t = 0;
     int rc = prepare_links(d);
+    if (rc) return rc;
+    rc = upload_phase(d, 0);
     if (rc) return rc;
     d->cur = 1;   // the init kernel writes into the "next" buffer of slot 1, i.e. buffer A
     lbm::StepArgs a = make_args(d);
@@ -484,7 +606,7 @@ int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
     d->cur = 0;
     d->t = 0;
     d->initialized = true;
-    d->stepped = false;
+    d->monitored = false;
     d->avg_count = 0;
     return LBM_OK;
 }
@@ -495,13 +617,23 @@ int lbm_step(lbm_domain* d, int nsteps) {
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
     int rc = prepare_links(d);
     if (rc) return rc;
-    for (int k = 0; k < nsteps; ++k) {
-        lbm::StepArgs a = make_args(d);
-        HIP_TRY(lbm::launch_step(d->storage, a, k == nsteps - 1, d->stream), "step kernel");
-        d->cur ^= 1;
-        d->t += 1;
+    int left = nsteps;
+    // Long runs replay captured graphs of GRAPH_STEPS launches (no host launch
+    // gaps); the default (NULL) stream cannot be captured and runs eagerly.
+    if (d->stream != nullptr) {
+        while (left >= GRAPH_STEPS) {
+            if (!d->graph[d->cur]) {
+                rc = build_graph(d);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(d->graph[d->cur], d->stream), "graph launch");
+            left -= GRAPH_STEPS;
+        }
     }
-    if (nsteps > 0) d->stepped = true;
+    rc = launch_steps_eager(d, left);
+    if (rc) return rc;
+    d->t += nsteps;
+    if (nsteps > 0) d->monitored = true;
     return LBM_OK;
 }
 
@@ -548,7 +680,7 @@ int lbm_average(lbm_domain* d, int op, double* u_avg) {
 
 int lbm_monitors(lbm_domain* d, double out[10]) {
     if (!d || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (!d->stepped) return fail(LBM_ESTATE, "no step has run since initialisation");
+    if (!d->monitored) return fail(LBM_ESTATE, "no step has run since initialisation");
     double* mo = (double*)(d->dev + d->off_monout);
     HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->nblocks, mo, d->stream),
             "monitor reduction");
@@ -573,14 +705,14 @@ namespace {
 struct StateHeader {
     char magic[8];
     uint32_t version, storage;
-    int64_t n, nspec, npad, t;
+    int64_t n, nspec, npad, t;   // nspec: number of open-boundary links
     uint64_t pop_bytes;
 };
 }  // namespace
 
 int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
-    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->spec.size() * 3 * sizeof(double);
+    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->nlinks() * sizeof(double);
     if (!host) {
         *bytes = need;
         return LBM_OK;
@@ -592,7 +724,7 @@ int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     h.version = 1;
     h.storage = (uint32_t)d->storage;
     h.n = d->n;
-    h.nspec = (int64_t)d->spec.size();
+    h.nspec = (int64_t)d->nlinks();
     h.npad = d->npad;
     h.t = d->t;
     h.pop_bytes = d->pop_bytes;
@@ -601,8 +733,8 @@ int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     const size_t cur_off = d->cur == 0 ? d->off_popA : d->off_popB;
     HIP_TRY(hipMemcpyAsync(p + sizeof h, d->dev + cur_off, d->pop_bytes, hipMemcpyDeviceToHost, d->stream),
             "state copy");
-    if (!d->spec.empty())
-        HIP_TRY(hipMemcpyAsync(p + sizeof h + d->pop_bytes, d->dev + d->off_uspec, d->spec.size() * 3 * sizeof(double),
+    if (d->nlinks())
+        HIP_TRY(hipMemcpyAsync(p + sizeof h + d->pop_bytes, d->dev + d->off_ladd, d->nlinks() * sizeof(double),
                                hipMemcpyDeviceToHost, d->stream), "state copy");
     HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");
     *bytes = need;
@@ -616,9 +748,9 @@ int lbm_set_state(lbm_domain* d, const void* host, size_t bytes) {
     StateHeader h;
     if (bytes < sizeof h) return fail(LBM_EINVAL, "state too short");
     std::memcpy(&h, host, sizeof h);
-    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->spec.size() * 3 * sizeof(double);
+    const size_t need = sizeof(StateHeader) + d->pop_bytes + d->nlinks() * sizeof(double);
     if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0 || h.version != 1 || h.storage != (uint32_t)d->storage ||
-        h.n != d->n || h.nspec != (int64_t)d->spec.size() || h.npad != d->npad || h.pop_bytes != d->pop_bytes ||
+        h.n != d->n || h.nspec != (int64_t)d->nlinks() || h.npad != d->npad || h.pop_bytes != d->pop_bytes ||
         h.t < 0 || bytes < need)
         return fail(LBM_EINVAL, "state header does not match this domain");
     int rc = prepare_links(d);
@@ -627,17 +759,19 @@ int lbm_set_state(lbm_domain* d, const void* host, size_t bytes) {
     d->cur = 0;
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_popA, p + sizeof h, d->pop_bytes, hipMemcpyHostToDevice, d->stream),
             "state upload");
-    if (!d->spec.empty())
-        HIP_TRY(hipMemcpyAsync(d->dev + d->off_uspec, p + sizeof h + d->pop_bytes, d->spec.size() * 3 * sizeof(double),
+    if (d->nlinks())
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_ladd, p + sizeof h + d->pop_bytes, d->nlinks() * sizeof(double),
                                hipMemcpyHostToDevice, d->stream), "state upload");
     d->t_upload[0] = h.t;
     d->t_upload[1] = h.t;
+    rc = upload_phase(d, h.t);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_tcount, d->t_upload, sizeof d->t_upload, hipMemcpyHostToDevice, d->stream),
             "state upload");
     HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");
     d->t = h.t;
     d->initialized = true;
-    d->stepped = false;
+    d->monitored = false;
     return LBM_OK;
 }
 

@@ -8,49 +8,59 @@
 
 namespace lbm {
 
-// Fluid-node descriptor word.  Ordinary node: x | y << 10 | z << 20.
-// Node that needs the general path (an open-boundary link or a link that wraps
-// around a periodic x axis): SPECIAL_BIT | index into the special table.
+// Fluid-node descriptor word (32 bits).
+//  - ordinary node, no periodic y/z axis: x | row << 10, row = (z+1)(ny+2) + (y+1)
+//  - ordinary node, periodic y or z axis:  x | y << 10 | z << 20
+//  - node that needs the general path (an open-boundary link, or a link that
+//    wraps around a periodic x axis): SPECIAL_BIT | index into the special table
 constexpr uint32_t SPECIAL_BIT = 0x80000000u;
 constexpr int MAX_DIM = 1023;
 constexpr int BLOCK = 256;            // threads per work-group of the step kernel
 constexpr int MON_WORDS = 10;         // doubles per work-group monitor partial
 
-// Source code of one incoming link of a special node.
-//   >= 0  : index of the fluid node the population is pulled from
-//   -1    : wall (halfway bounce-back)
-//   <= -2 : open-boundary link, index (-2 - code) into the link table
-constexpr int32_t SRC_WALL = -1;
+// Row table entry: fluid bitmap word of a row (bit x + 1 for cell x) and the
+// number of fluid nodes before that word in list (x-fastest) order.
+struct alignas(8) RowEntry {
+    uint32_t bits;
+    int32_t prefix;
+};
 
+// Record of a node with open-boundary or periodic-x links.  off[alpha] is the
+// byte offset (from the population buffer) of the value it pulls: the source
+// node's alpha population for a fluid link, its own abar population for a wall
+// or open link (bounce-back).  Open links then get the boundary correction:
+// inlet f += add, outlet f = -f + add.  Links are numbered from link0 in
+// increasing alpha.
 struct alignas(16) SpecialNode {
+    uint32_t off[27];
     int32_t node;          // fluid-node index
-    int32_t x, y, z;
-    int32_t src[27];
-    int32_t pad;
+    int32_t link0;         // first open-boundary link of this node
+    uint32_t wallmask;     // bit alpha: wall link
+    uint32_t linkmask;     // bit alpha: open-boundary link
 };
 static_assert(sizeof(SpecialNode) == 128, "special node record is 128 bytes");
 
 enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3 };
 
-struct alignas(16) BcLink {
-    int32_t type;          // LINK_INLET or LINK_OUTLET
-    int32_t pad;
-    double a0;             // inlet: steady axial speed at the link midpoint
-    double a1re, a1im;     // inlet: complex oscillating amplitude
-};
-static_assert(sizeof(BcLink) == 32, "link record is 32 bytes");
-
-// Kernel arguments of one step over one domain (passed by value).
+// Per open-boundary link: meta = type | alpha << 8; coef = (a0, a1re, a1im,
+// k1, k3, k5): the inlet speed at the link midpoint is
+// U = a0 + a1re cos(omega t) - a1im sin(omega t), and the moving-wall term
+// f_eq_a(1, axis U) - f_eq_abar(1, axis U) equals the odd polynomial
+// U (k1 + U^2 (k3 + U^2 k5)) exactly; add = additive term of the incoming
+// population for the next step (inlet: that moving-wall term; outlet:
+// f_eq_a + f_eq_abar - 2 w_a at rho_out and the node's velocity).
+constexpr int LINK_COEFS = 6;
 struct StepArgs {
     const void* fin;             // post-collision populations of time t  [27][npad]
     void* fout;                  // post-collision populations of time t+1
     const uint32_t* node;        // [npad] descriptor words
-    const uint32_t* bits;        // [rows][W] fluid bitmap, bit (x + 1) of row (y, z)
-    const int32_t* prefix;       // [rows][W] fluid nodes before each bitmap word
+    const RowEntry* rowtab;      // [rows][W]
     const SpecialNode* spec;     // [nspec]
-    const BcLink* links;         // [nlinks]
-    double* u_spec;              // [nspec][3] velocity of each special node's last collision
+    const int32_t* link_meta;    // [nlinks]
+    const double* link_coef;     // [nlinks][LINK_COEFS]
+    double* link_add;            // [nlinks]
     int64_t* tcount;             // [2] time counters (read slot tin, write slot tin ^ 1)
+    double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials
     int tin;
     int n, npad, nx, ny, nz, W, periodic;
@@ -58,12 +68,20 @@ struct StepArgs {
     double s[5];                 // relaxation rates of orders 2..6
     double g[3];                 // body acceleration
     double omega;                // inlet angular frequency
+    double cos_w, sin_w;         // cos(omega), sin(omega): one-step rotation of the inlet phase
     double axis[3];              // inlet direction (unit)
     double rho_out;              // outlet density
 };
 
+// Kernel variant of a step: which collision and which monitors.
+struct StepVariant {
+    bool monitor;        // accumulate the FP64 monitors (mass, momentum, wall force, fluxes)
+    bool rates_one;      // free rates of orders 3..6 all equal to 1
+    bool periodic_yz;    // a periodic y or z axis (node words hold x, y, z)
+};
+
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
-hipError_t launch_step(int storage, const StepArgs& a, bool full, hipStream_t stream);
+hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream);
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream);
 hipError_t launch_moments(int storage, const StepArgs& a, double* rho, double* u, double* avg,

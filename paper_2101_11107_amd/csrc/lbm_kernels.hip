@@ -5,18 +5,20 @@
 // previous step from the structure-of-arrays buffer (halfway bounce-back for
 // wall links, Eq. (9) at q = 1/2; inlet/outlet rules for open links), forms
 // rho and j (Eqs. (4)-(5)), applies the central Hermite moment collision
-// (Eq. (6) with the equilibrium moments of Eq. (8)) with three one-dimensional
-// transforms per direction in registers, and stores the 27 post-collision
-// populations.  All populations are stored shifted by their weights
-// (f - w_alpha) and the collision works on deviations, so every intermediate
-// value is small and reduced-precision storage keeps its relative accuracy.
+// (Eq. (6) with the equilibrium central moments (rho, 0, ..., 0) of Eq. (8)) in
+// registers with one-dimensional transforms along x, y and z, and stores the
+// 27 post-collision populations.  Populations are stored shifted by their
+// weights (f - w_alpha) and the collision works on deviations, so every
+// intermediate value is small and reduced-precision storage keeps its relative
+// accuracy.
 //
-// Addressing: the neighbour of node (x, y, z) in row (y', z') is located from
-// a fluid bitmap of the box and a per-word prefix count (the number of fluid
-// nodes before that bitmap word in x-fastest order): the index of cell
-// (x', y', z') is prefix + popcount of the preceding bits.  Only 4 bytes per
-// node (its packed coordinates) are streamed besides the populations; the
-// bitmap words are shared by a whole wavefront and stay in cache.
+// Addressing: a node's neighbours in row (y', z') are located through a row
+// table that holds, per 32 cells, the fluid bitmap word and the number of fluid
+// nodes before it in x-fastest order: the index of fluid cell (x', y', z') is
+// that count plus the popcount of the preceding bits.  Besides the populations
+// only one 4-byte descriptor per node is streamed; the row table is shared by a
+// wavefront and stays in cache.  Loads use 32-bit byte offsets from a uniform
+// base, so each population address costs one or two integer operations.
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -34,24 +36,34 @@ __host__ __device__ constexpr double wgt(int a) { return w1d(cxo(a)) * w1d(cyo(a
 template <class S> struct Traits;
 template <> struct Traits<double> {
     using T = double;
-    __device__ static T ld(const double* p, uint32_t k) { return p[k]; }
-    __device__ static void st(double* p, uint32_t k, T v) { p[k] = v; }
+    __device__ static T cvt(double v) { return v; }
+    __device__ static double store(T v) { return v; }
 };
 template <> struct Traits<float> {
     using T = float;
-    __device__ static T ld(const float* p, uint32_t k) { return p[k]; }
-    __device__ static void st(float* p, uint32_t k, T v) { p[k] = v; }
+    __device__ static T cvt(float v) { return v; }
+    __device__ static float store(T v) { return v; }
 };
 template <> struct Traits<_Float16> {
     using T = float;
-    __device__ static T ld(const _Float16* p, uint32_t k) { return (float)p[k]; }
-    __device__ static void st(_Float16* p, uint32_t k, T v) { p[k] = (_Float16)v; }   // RNE
+    __device__ static T cvt(_Float16 v) { return (float)v; }
+    __device__ static _Float16 store(T v) { return (_Float16)v; }    // round to nearest even
 };
 template <> struct Traits<__bf16> {
     using T = float;
-    __device__ static T ld(const __bf16* p, uint32_t k) { return (float)p[k]; }
-    __device__ static void st(__bf16* p, uint32_t k, T v) { p[k] = (__bf16)v; }       // RNE
+    __device__ static T cvt(__bf16 v) { return (float)v; }
+    __device__ static __bf16 store(T v) { return (__bf16)v; }        // round to nearest even
 };
+
+// Load / store of one population at a byte offset from a uniform base.
+template <class S>
+__device__ __forceinline__ typename Traits<S>::T ldp(const char* __restrict__ base, uint32_t off) {
+    return Traits<S>::cvt(*(const S*)(base + off));
+}
+template <class S>
+__device__ __forceinline__ void stp(char* __restrict__ base, uint32_t off, typename Traits<S>::T v) {
+    *(S*)(base + off) = Traits<S>::store(v);
+}
 
 // Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
 __device__ inline double feq1(int a, double rho, const double u[3]) {
@@ -65,7 +77,7 @@ __device__ inline double feq1(int a, double rho, const double u[3]) {
     return r;
 }
 
-// --- central Hermite transforms (one line of three populations) ---------------------
+// --- central Hermite transforms on one line (c = -1, 0, +1) ---------------------
 // Forward: (f-, f0, f+) -> (m0, m1, m2) with H0 = 1, H1 = c - u, H2 = (c - u)^2 - 1/3.
 template <class T>
 __device__ __forceinline__ void fwd1(T& a, T& b, T& c, T u, T u2m) {
@@ -86,22 +98,47 @@ __device__ __forceinline__ void inv1(T& a, T& b, T& c, T u, T u2p) {
     b = m0 - r2;
     c = T(0.5) * (r2 + r1);
 }
-
-// Collision of the shifted populations f (= f - w) in place; returns u.
-// Deviation form: with dA = T(u) f_hat and (T w)_ijk = p_i(ux) p_j(uy) p_k(uz),
-// p = (1, -u, u^2), the post-collision deviations are
-//   order 0: d rho;  order 1: rho g / 2 + u;  order n >= 2: (1 - s_n) dA - s_n (T w),
-// and f_hat* = T(u)^-1 of them.
+// Inverse with the first- and second-order inputs given at half scale
+// (b = m1/2, c = m2/2): k = r1/2, h = r2/2, f- = h - k, f0 = m0 - 2h, f+ = h + k.
 template <class T>
-__device__ __forceinline__ void collide(T (&f)[27], T drho, T jx, T jy, T jz,
-                                        const T (&om)[5], const T (&sr)[5], const T (&g)[3],
-                                        T& ux, T& uy, T& uz) {
-    const T rho = T(1) + drho;
-    const T inv = T(1) / rho;
-    const T hr = T(0.5) * rho;
-    ux = (jx + hr * g[0]) * inv;
-    uy = (jy + hr * g[1]) * inv;
-    uz = (jz + hr * g[2]) * inv;
+__device__ __forceinline__ void inv1h(T& a, T& b, T& c, T uh, T u2, T u2ph) {
+    const T k = b + uh * a;                   // uh = u/2
+    const T h = c + u2 * b + u2ph * a;        // u2 = 2u, u2ph = (u^2 + 1/3)/2
+    const T m0 = a;
+    a = h - k;
+    b = m0 - T(2) * h;
+    c = h + k;
+}
+
+// Line sums over x for the nine (cy, cz) lines q = 3 (cz + 1) + (cy + 1).
+template <class T>
+__device__ __forceinline__ void line_sums(const T (&f)[27], T (&S0)[9], T (&S1)[9], T (&S2)[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        S1[q] = f[3 * q + 2] - f[3 * q];
+        S2[q] = f[3 * q + 2] + f[3 * q];
+        S0[q] = S2[q] + f[3 * q + 1];
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void conserved(const T (&S0)[9], const T (&S1)[9], T& drho, T& jx, T& jy, T& jz) {
+    // rho - 1 and j of the shifted populations (sum w = 1, sum w c = 0)
+    const T zm = S0[0] + S0[1] + S0[2], z0 = S0[3] + S0[4] + S0[5], zp = S0[6] + S0[7] + S0[8];
+    const T ym = S0[0] + S0[3] + S0[6], yp = S0[2] + S0[5] + S0[8];
+    drho = (zm + z0) + zp;
+    jx = ((S1[0] + S1[1]) + (S1[2] + S1[3])) + ((S1[4] + S1[5]) + (S1[6] + S1[7])) + S1[8];
+    jy = yp - ym;
+    jz = zp - zm;
+}
+
+// General collision (any free rates), deviation form.  With dA = T(u) f_hat and
+// (T w)_ijk = p_i(ux) p_j(uy) p_k(uz), p = (1, -u, u^2), the post-collision
+// deviations are: order 0: d rho; order 1: rho g / 2 + u; order n >= 2:
+// (1 - s_n) dA - s_n (T w); then f_hat* = T(u)^-1 of them.
+template <class T>
+__device__ __forceinline__ void collide_general(T (&f)[27], T drho, T ux, T uy, T uz, T hr,
+                                                const T (&om)[5], const T (&sr)[5], const T (&g)[3]) {
     const T third = T(1) / T(3);
     const T xm = ux * ux - third, ym = uy * uy - third, zm = uz * uz - third;
 #pragma unroll
@@ -140,109 +177,240 @@ __device__ __forceinline__ void collide(T (&f)[27], T drho, T jx, T jy, T jz,
     for (int q = 0; q < 9; ++q) inv1(f[3 * q], f[3 * q + 1], f[3 * q + 2], ux, xp);
 }
 
+// Collision when the free rates of orders 3..6 all equal 1: those moments
+// relax fully to equilibrium, so only the six second-order central moments of
+// the incoming populations are needed.  They follow from the raw second
+// moments P of f_hat:  dA_ab = P_ab - u_a j_b - u_b j_a + u_a u_b d rho
+// - delta_ab d rho / 3.  Post-collision deviations: order 0 d rho, order 1
+// rho g / 2 + u, order 2 (1 - s2) dA - s2 (T w), orders 3..6 -(T w).  The
+// inverse runs with every moment scaled by 1/2 per non-zero index (inv1h).
 template <class T>
-__device__ __forceinline__ void sums(const T (&f)[27], T& drho, T& jx, T& jy, T& jz) {
-    // rho - 1 and j of the shifted populations (sum w = 1, sum w c = 0).
-    T s[9];
+__device__ __forceinline__ void collide_rates_one(T (&f)[27], const T (&S0)[9], const T (&S1)[9],
+                                                  const T (&S2)[9], T drho, T jx, T jy, T jz,
+                                                  T ux, T uy, T uz, T hr, T om2, T s2,
+                                                  const T (&g)[3]) {
+    const T third = T(1) / T(3);
+    const T Pxx = ((S2[0] + S2[1]) + (S2[2] + S2[3])) + ((S2[4] + S2[5]) + (S2[6] + S2[7])) + S2[8];
+    const T Pxy = (S1[2] + S1[5] + S1[8]) - (S1[0] + S1[3] + S1[6]);
+    const T Pxz = (S1[6] + S1[7] + S1[8]) - (S1[0] + S1[1] + S1[2]);
+    const T Pyy = (S0[0] + S0[2]) + (S0[3] + S0[5]) + (S0[6] + S0[8]);
+    const T Pzz = (S0[0] + S0[1]) + (S0[2] + S0[6]) + (S0[7] + S0[8]);
+    const T Pyz = (S0[0] + S0[8]) - (S0[2] + S0[6]);
+    const T d3 = drho * third;
+    const T dxx = Pxx - T(2) * ux * jx + (ux * ux) * drho - d3;
+    const T dyy = Pyy - T(2) * uy * jy + (uy * uy) * drho - d3;
+    const T dzz = Pzz - T(2) * uz * jz + (uz * uz) * drho - d3;
+    const T dxy = Pxy - ux * jy - uy * jx + (ux * uy) * drho;
+    const T dxz = Pxz - ux * jz - uz * jx + (ux * uz) * drho;
+    const T dyz = Pyz - uy * jz - uz * jy + (uy * uz) * drho;
+
+    // half-scaled p: q = (1, -u/2, u^2/2)
+    const T qx[3] = {T(1), T(-0.5) * ux, T(0.5) * ux * ux};
+    const T qy[3] = {T(1), T(-0.5) * uy, T(0.5) * uy * uy};
+    const T qz[3] = {T(1), T(-0.5) * uz, T(0.5) * uz * uz};
+    const T hom2 = T(0.5) * om2, qom2 = T(0.25) * om2;
+    T m[27];
+    m[0] = drho;
+    m[1] = T(0.5) * (hr * g[0] + ux);
+    m[3] = T(0.5) * (hr * g[1] + uy);
+    m[9] = T(0.5) * (hr * g[2] + uz);
+    // order 2, scaled by 1/2 (one non-zero index) or 1/4 (two)
+    m[2] = hom2 * dxx - s2 * qx[2];
+    m[6] = hom2 * dyy - s2 * qy[2];
+    m[18] = hom2 * dzz - s2 * qz[2];
+    m[4] = qom2 * dxy - s2 * (qx[1] * qy[1]);
+    m[10] = qom2 * dxz - s2 * (qx[1] * qz[1]);
+    m[12] = qom2 * dyz - s2 * (qy[1] * qz[1]);
+    // orders 3..6 with 1 - s = 0: -(T w), scaled
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s[q] = f[3 * q] + f[3 * q + 1] + f[3 * q + 2];
-    T x = T(0);
+    for (int mm = 0; mm < 27; ++mm) {
+        const int i = mm % 3, j = (mm / 3) % 3, k = mm / 9;
+        if (i + j + k >= 3) m[mm] = -(qx[i] * qy[j]) * qz[k];
+    }
+    const T uhz = T(0.5) * uz, u2z = T(2) * uz, u2pz = T(0.5) * (uz * uz + third);
+    const T uhy = T(0.5) * uy, u2y = T(2) * uy, u2py = T(0.5) * (uy * uy + third);
+    const T uhx = T(0.5) * ux, u2x = T(2) * ux, u2px = T(0.5) * (ux * ux + third);
+    // z pass; the lines (i, j) with i + j >= 3 hold -(T w) only and invert to
+    // -(q_i q_j) w1(cz)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) x += f[3 * q + 2] - f[3 * q];
-    const T zm = s[0] + s[1] + s[2], z0 = s[3] + s[4] + s[5], zp = s[6] + s[7] + s[8];
-    const T ym = s[0] + s[3] + s[6], yp = s[2] + s[5] + s[8];
-    drho = zm + z0 + zp;
-    jx = x;
-    jy = yp - ym;
-    jz = zp - zm;
+    for (int q = 0; q < 9; ++q) {
+        const int i = q % 3, j = q / 3;
+        if (i + j >= 3) {
+            const T P = qx[i] * qy[j];
+            const T e = P * T(-1.0 / 6.0);
+            m[q] = e;
+            m[q + 9] = P * T(-2.0 / 3.0);
+            m[q + 18] = e;
+        } else {
+            inv1h(m[q], m[q + 9], m[q + 18], uhz, u2z, u2pz);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) inv1h(m[9 * k + i], m[9 * k + i + 3], m[9 * k + i + 6], uhy, u2y, u2py);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) inv1h(m[3 * q], m[3 * q + 1], m[3 * q + 2], uhx, u2x, u2px);
+#pragma unroll
+    for (int mm = 0; mm < 27; ++mm) f[mm] = m[mm];
 }
 
-// --- gather of the incoming populations ---------------------------------------------
-template <class S>
-__device__ __forceinline__ void gather_fast(const S* __restrict__ fin, const StepArgs& a, int i,
+// --- gather of the incoming populations -------------------------------------------
+struct __attribute__((aligned(8))) RowPair {
+    uint32_t w0;
+    int32_t p0;
+    uint32_t w1;
+    int32_t p1;
+};
+
+// Ordinary node: streaming and halfway bounce-back through the row table.
+template <class S, bool PER, bool WALLS>
+__device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const StepArgs& a, int i,
                                             uint32_t w, typename Traits<S>::T (&f)[27],
                                             uint32_t& wallmask) {
-    const int x = w & 1023, y = (w >> 10) & 1023, z = (w >> 20) & 1023;
-    const int wl = x >> 5, sh = x & 31;
+    constexpr uint32_t SZ = sizeof(S);
+    const uint32_t plane = (uint32_t)a.npad * SZ;
+    const uint32_t ib = (uint32_t)i * SZ;
+    const char* rt = (const char*)a.rowtab;
+    const int x = (int)(w & 1023u);
+    int y = 0, z = 0;
+    uint32_t e0 = 0;
+    if (!PER) {
+        e0 = (w >> 10) * (uint32_t)a.W + (uint32_t)(x >> 5);
+    } else {
+        y = (int)((w >> 10) & 1023u);
+        z = (int)((w >> 20) & 1023u);
+    }
+    const uint32_t sh = (uint32_t)x & 31u;
     const uint32_t low = (uint32_t)((2ull << sh) - 1ull);
-    const uint32_t np = (uint32_t)a.npad;
     const int rowlen = a.ny + 2;
 #pragma unroll
     for (int kz = 0; kz < 3; ++kz) {
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
-            int ys = y - (ky - 1), zs = z - (kz - 1);
-            if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
-            if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
-            const uint32_t row = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + wl;
-            const uint32_t w0 = a.bits[row], w1 = a.bits[row + 1];
-            const uint32_t b3 = (uint32_t)(((((uint64_t)w1) << 32) | w0) >> sh) & 7u;
-            int base;
-            if (ky == 1 && kz == 1) base = i;
-            else base = a.prefix[row] + __popc(w0 & low);
+            uint32_t e;
+            if (!PER) {
+                e = e0 - (uint32_t)(((ky - 1) + (kz - 1) * rowlen) * a.W);
+            } else {
+                int ys = y - (ky - 1), zs = z - (kz - 1);
+                if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
+                if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
+                e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
+            }
+            const RowPair rp = *(const RowPair*)(rt + e * 8u);
+            // bits of cells x - 1, x, x + 1 of this row
+            const uint32_t win = __builtin_amdgcn_alignbit(rp.w1, rp.w0, sh);
+            const int base = (ky == 1 && kz == 1) ? i : rp.p0 + (int)__popc(rp.w0 & low);
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
                 const int al = 9 * kz + 3 * ky + kx;
                 const int k = 2 - kx;              // bit of the source cell x - cx
-                const bool fl = (b3 >> k) & 1u;
-                const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((b3 >> 1) & 1u));
-                const uint32_t addr = fl ? (uint32_t)al * np + (uint32_t)src
-                                         : (uint32_t)(26 - al) * np + (uint32_t)i;
-                f[al] = Traits<S>::ld(fin, addr);
-                if (!fl) wallmask |= 1u << al;
+                if (al == 13) {
+                    f[al] = ldp<S>(fin, 13u * plane + ib);
+                    continue;
+                }
+                const bool fl = (win >> k) & 1u;
+                const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
+                const uint32_t off = fl ? (uint32_t)al * plane + (uint32_t)src * SZ
+                                        : (uint32_t)(26 - al) * plane + ib;
+                f[al] = ldp<S>(fin, off);
+                if (WALLS && !fl) wallmask |= 1u << al;
             }
         }
     }
 }
 
-template <class S>
-__device__ __forceinline__ void gather_special(const S* __restrict__ fin, const StepArgs& a, int i,
-                                            int sidx, typename Traits<S>::T (&f)[27], double (&F)[3],
-                                            double& qin, double& qout) {
+// Node with open-boundary or periodic-x links: explicit byte offsets, then the
+// open-boundary corrections with the additive terms prepared by the previous
+// step (or the initial state): inlet f_a = f*_abar + add, outlet
+// f_a = -f*_abar + add (evaluated in FP64, rounded once).
+template <class S, bool MON>
+__device__ __forceinline__ void gather_special(const char* __restrict__ fin, const StepArgs& a,
+                                               const SpecialNode* __restrict__ sp,
+                                               typename Traits<S>::T (&f)[27], double (&F)[3],
+                                               double& qin, double& qout) {
     using T = typename Traits<S>::T;
-    const SpecialNode* sp = a.spec + sidx;
-    const uint32_t np = (uint32_t)a.npad;
-    const int64_t t = a.tcount[a.tin];
-    double cw = 1.0, sw = 0.0;
-    bool have_trig = false;
 #pragma unroll
-    for (int al = 0; al < 27; ++al) {
-        const int code = sp->src[al];
-        if (code >= 0) {
-            f[al] = Traits<S>::ld(fin, (uint32_t)al * np + (uint32_t)code);
-            continue;
-        }
-        const T own_t = Traits<S>::ld(fin, (uint32_t)(26 - al) * np + (uint32_t)i);
-        const double own = (double)own_t;
-        if (code == SRC_WALL) {
-            f[al] = own_t;
-            const double v = 2.0 * (own + wgt(al));
-            F[0] -= v * cxo(al);
-            F[1] -= v * cyo(al);
-            F[2] -= v * czo(al);
-            continue;
-        }
-        const BcLink L = a.links[-2 - code];
-        double val;
-        if (L.type == LINK_INLET) {
-            if (!have_trig) {
-                sincos(a.omega * (double)t, &sw, &cw);
-                have_trig = true;
+    for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin, sp->off[al]);
+    const uint32_t wm = sp->wallmask, lm = sp->linkmask;
+    if (MON && wm) {
+#pragma unroll
+        for (int al = 0; al < 27; ++al) {
+            if ((wm >> al) & 1u) {
+                const double v = 2.0 * ((double)f[al] + wgt(al));
+                F[0] -= v * cxo(al);
+                F[1] -= v * cyo(al);
+                F[2] -= v * czo(al);
             }
-            const double spd = L.a0 + L.a1re * cw - L.a1im * sw;
-            const double uw[3] = {a.axis[0] * spd, a.axis[1] * spd, a.axis[2] * spd};
-            val = own + (feq1(al, 1.0, uw) - feq1(26 - al, 1.0, uw));
-            const T vt = (T)val;
-            f[al] = vt;
-            qin += (double)vt - own;
-        } else {
-            const double ux[3] = {a.u_spec[3 * sidx], a.u_spec[3 * sidx + 1], a.u_spec[3 * sidx + 2]};
-            val = -own + ((feq1(al, a.rho_out, ux) - wgt(al)) + (feq1(26 - al, a.rho_out, ux) - wgt(al)));
-            const T vt = (T)val;
-            f[al] = vt;
-            qout += (double)vt - own;
         }
     }
+    if (lm) {
+        int l = sp->link0;
+#pragma unroll
+        for (int al = 0; al < 27; ++al) {
+            if ((lm >> al) & 1u) {
+                const bool inlet = (a.link_meta[l] & 0xff) == LINK_INLET;
+                const double own = (double)f[al];
+                const T vt = (T)((inlet ? own : -own) + a.link_add[l]);
+                f[al] = vt;
+                if (MON) {
+                    const double q = (double)vt - own;
+                    if (inlet) qin += q;
+                    else qout += q;
+                }
+                ++l;
+            }
+        }
+    }
+}
+
+// Additive terms of a special node's open links for the step that streams the
+// populations of time t_next.  The inlet phase (cos, sin)(omega t_next) is read
+// from the device phase slots.
+__device__ __forceinline__ void update_links(const StepArgs& a, const SpecialNode* __restrict__ sp, double ux,
+                                          double uy, double uz, int64_t t_next) {
+    const int l0 = sp->link0, nl = __popc(sp->linkmask);
+    const double cw = a.trig[2 * (t_next & 1)], sw = a.trig[2 * (t_next & 1) + 1];
+    for (int l = l0; l < l0 + nl; ++l) {
+        const int meta = a.link_meta[l];
+        const int al = meta >> 8;
+        const double* cf = a.link_coef + LINK_COEFS * l;
+        double add;
+        if ((meta & 0xff) == LINK_INLET) {
+            const double U = cf[0] + cf[1] * cw - cf[2] * sw;
+            const double U2 = U * U;
+            add = U * (cf[3] + U2 * (cf[4] + U2 * cf[5]));
+        } else {
+            // f_eq_a + f_eq_abar = 2 rho_out (even part of prod_d (e_d + o_d)),
+            // e_d, o_d the even and odd parts of psi(c_d, u_d)
+            const int c[3] = {al % 3 - 1, (al / 3) % 3 - 1, al / 9 - 1};
+            const double u[3] = {ux, uy, uz};
+            double e[3], o[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double v = u[d];
+                e[d] = c[d] == 0 ? 2.0 / 3.0 - v * v : 0.5 * (1.0 / 3.0 + v * v);
+                o[d] = c[d] == 0 ? 0.0 : 0.5 * c[d] * v;
+            }
+            const double even = e[0] * e[1] * e[2] + e[0] * o[1] * o[2] + o[0] * e[1] * o[2] + o[0] * o[1] * e[2];
+            const double w = (c[0] == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (c[1] == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
+                             (c[2] == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
+            add = 2.0 * (a.rho_out * even - w);
+        }
+        a.link_add[l] = add;
+    }
+}
+
+// Advance the inlet phase: slot (t + 2) & 1 <- rotation of slot (t + 1) & 1 by
+// omega, renormalized to unit length.
+__device__ __forceinline__ void advance_phase(const StepArgs& a, int64_t t) {
+    const double* p = a.trig + 2 * ((t + 1) & 1);
+    const double c = p[0] * a.cos_w - p[1] * a.sin_w;
+    const double s = p[1] * a.cos_w + p[0] * a.sin_w;
+    const double r = 1.0 / sqrt(c * c + s * s);
+    double* q = a.trig + 2 * ((t + 2) & 1);
+    q[0] = c * r;
+    q[1] = s * r;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -251,7 +419,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Fixed-order block reduction of 9 monitor values into partials[lb].
+// Fixed-order block reduction of 9 monitor values into out[0..8].
 __device__ __forceinline__ void block_monitor(double (&m)[9], double* __restrict__ out) {
     __shared__ double red[BLOCK / 64][9];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -270,46 +438,63 @@ __device__ __forceinline__ void block_monitor(double (&m)[9], double* __restrict
     }
 }
 
-template <class T>
-__device__ __forceinline__ void load_rates(const StepArgs& a, T (&om)[5], T (&sr)[5], T (&g)[3]) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        sr[k] = (T)a.s[k];
-        om[k] = (T)(1.0 - a.s[k]);
-    }
+// Collision of the gathered populations (in place): moments, then one of the
+// two collision forms.  Returns the velocity and the conserved sums.
+template <class T, bool ONE>
+__device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T& uy, T& uz, T& drho,
+                                        T& jx, T& jy, T& jz) {
+    T S0[9], S1[9], S2[9];
+    line_sums(f, S0, S1, S2);
+    conserved(S0, S1, drho, jx, jy, jz);
+    T g[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) g[d] = (T)a.g[d];
+    const T rho = T(1) + drho;
+    const T inv = T(1) / rho;
+    const T hr = T(0.5) * rho;
+    ux = (jx + hr * g[0]) * inv;
+    uy = (jy + hr * g[1]) * inv;
+    uz = (jz + hr * g[2]) * inv;
+    if (ONE) {
+        collide_rates_one(f, S0, S1, S2, drho, jx, jy, jz, ux, uy, uz, hr, (T)(1.0 - a.s[0]), (T)a.s[0], g);
+    } else {
+        T om[5], sr[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            sr[k] = (T)a.s[k];
+            om[k] = (T)(1.0 - a.s[k]);
+        }
+        collide_general(f, drho, ux, uy, uz, hr, om, sr, g);
+    }
 }
 
 // --- the step kernel ----------------------------------------------------------------
-// FULL = true also accumulates the wall force (momentum given to the walls).
-template <class S, bool FULL>
+template <class S, bool MON, bool ONE, bool PER>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
     using T = typename Traits<S>::T;
+    constexpr uint32_t SZ = sizeof(S);
     // XCD-aware order: hardware work-group b runs on XCD (b % 8); give each XCD
     // a contiguous range of the node list so neighbour rows share its L2.
     const int hb = blockIdx.x;
     const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
     if (lb >= a.nblocks) return;
     const int i = lb * BLOCK + threadIdx.x;
-    const S* __restrict__ fin = (const S*)a.fin;
-    S* __restrict__ fout = (S*)a.fout;
+    const char* __restrict__ fin = (const char*)a.fin;
+    char* __restrict__ fout = (char*)a.fout;
     double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < a.n) {
         T f[27];
         uint32_t wallmask = 0;
         double F[3] = {0.0, 0.0, 0.0}, qin = 0.0, qout = 0.0;
         const uint32_t w = a.node[i];
-        int sidx = -1;
+        const SpecialNode* sp = nullptr;
         if (!(w & SPECIAL_BIT)) {
-            gather_fast<S>(fin, a, i, w, f, wallmask);
+            gather_fast<S, PER, MON>(fin, a, i, w, f, wallmask);
         } else {
-            sidx = (int)(w & ~SPECIAL_BIT);
-            gather_special<S>(fin, a, i, sidx, f, F, qin, qout);
+            sp = a.spec + (w & ~SPECIAL_BIT);
+            gather_special<S, MON>(fin, a, sp, f, F, qin, qout);
         }
-        T drho, jx, jy, jz;
-        sums(f, drho, jx, jy, jz);
-        if (FULL && wallmask) {
+        if (MON && wallmask) {
             T fx = T(0), fy = T(0), fz = T(0);
 #pragma unroll
             for (int al = 0; al < 27; ++al) {
@@ -323,40 +508,45 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
             F[1] -= 2.0 * (double)fy;
             F[2] -= 2.0 * (double)fz;
         }
-        mon[0] = (double)drho;
-        mon[1] = (double)jx;
-        mon[2] = (double)jy;
-        mon[3] = (double)jz;
-        mon[4] = F[0];
-        mon[5] = F[1];
-        mon[6] = F[2];
-        mon[7] = qin;
-        mon[8] = qout;
-        T om[5], sr[5], g[3];
-        load_rates(a, om, sr, g);
-        T ux, uy, uz;
-        collide(f, drho, jx, jy, jz, om, sr, g, ux, uy, uz);
-        if (sidx >= 0) {
-            a.u_spec[3 * sidx] = (double)ux;
-            a.u_spec[3 * sidx + 1] = (double)uy;
-            a.u_spec[3 * sidx + 2] = (double)uz;
+        T ux, uy, uz, drho, jx, jy, jz;
+        collide<T, ONE>(f, a, ux, uy, uz, drho, jx, jy, jz);
+        if (MON) {
+            mon[0] = (double)drho;
+            mon[1] = (double)jx;
+            mon[2] = (double)jy;
+            mon[3] = (double)jz;
+            mon[4] = F[0];
+            mon[5] = F[1];
+            mon[6] = F[2];
+            mon[7] = qin;
+            mon[8] = qout;
         }
-        const uint32_t np = (uint32_t)a.npad;
+        const uint32_t plane = (uint32_t)a.npad * SZ;
+        const uint32_t ib = (uint32_t)i * SZ;
 #pragma unroll
-        for (int al = 0; al < 27; ++al) Traits<S>::st(fout, (uint32_t)al * np + (uint32_t)i, f[al]);
+        for (int al = 0; al < 27; ++al) stp<S>(fout, (uint32_t)al * plane + ib, f[al]);
+        // after the stores, so the populations are no longer live
+        if (sp != nullptr && sp->linkmask != 0u)
+            update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);
     }
-    if (lb == 0 && threadIdx.x == 0) a.tcount[a.tin ^ 1] = a.tcount[a.tin] + 1;
-    block_monitor(mon, a.partials + (size_t)lb * MON_WORDS);
+    if (lb == 0 && threadIdx.x == 0) {
+        const int64_t t = a.tcount[a.tin];
+        a.tcount[a.tin ^ 1] = t + 1;
+        advance_phase(a, t);
+    }
+    if (MON) block_monitor(mon, a.partials + (size_t)lb * MON_WORDS);
 }
 
-// Initial state: f(0) = f_eq(rho, u), then the first collision; written to fout.
+// Initial state: f(0) = f_eq(rho, u), then the first collision (written to
+// fout), and the open-link terms for the first step.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, const double* u0) {
     using T = typename Traits<S>::T;
+    constexpr uint32_t SZ = sizeof(S);
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i == 0) {
-        a.tcount[a.tin] = 0;
-        a.tcount[a.tin ^ 1] = 0;
+        a.tcount[0] = 0;
+        a.tcount[1] = 0;
     }
     if (i >= a.n) return;
     const double r = rho0 ? rho0[i] : 1.0;
@@ -364,23 +554,20 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
     T f[27];
 #pragma unroll
     for (int al = 0; al < 27; ++al) f[al] = (T)(feq1(al, r, u) - wgt(al));
-    T drho, jx, jy, jz;
-    sums(f, drho, jx, jy, jz);
-    T om[5], sr[5], g[3];
-    load_rates(a, om, sr, g);
-    T ux, uy, uz;
-    collide(f, drho, jx, jy, jz, om, sr, g, ux, uy, uz);
+    T ux, uy, uz, drho, jx, jy, jz;
+    if (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0)
+        collide<T, true>(f, a, ux, uy, uz, drho, jx, jy, jz);
+    else
+        collide<T, false>(f, a, ux, uy, uz, drho, jx, jy, jz);
     const uint32_t w = a.node[i];
     if (w & SPECIAL_BIT) {
-        const int sidx = (int)(w & ~SPECIAL_BIT);
-        a.u_spec[3 * sidx] = (double)ux;
-        a.u_spec[3 * sidx + 1] = (double)uy;
-        a.u_spec[3 * sidx + 2] = (double)uz;
+        const SpecialNode* sp = a.spec + (w & ~SPECIAL_BIT);
+        if (sp->linkmask != 0u) update_links(a, sp, (double)ux, (double)uy, (double)uz, 0);
     }
-    S* fout = (S*)a.fout;
-    const uint32_t np = (uint32_t)a.npad;
+    char* fout = (char*)a.fout;
+    const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
-    for (int al = 0; al < 27; ++al) Traits<S>::st(fout, (uint32_t)al * np + (uint32_t)i, f[al]);
+    for (int al = 0; al < 27; ++al) stp<S>(fout, (uint32_t)al * plane + (uint32_t)i * SZ, f[al]);
 }
 
 // rho and u of the current state from the post-collision populations, in FP64:
@@ -389,6 +576,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, double* rho, double* u, double* avg,
                                                   int mode, double count) {
+    constexpr uint32_t SZ = sizeof(S);
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const int n = a.n;
@@ -399,12 +587,12 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, double* rho, doub
         u[2 * n + i] = avg[2 * n + i] * inv;
         return;
     }
-    const S* fin = (const S*)a.fin;
-    const uint32_t np = (uint32_t)a.npad;
+    const char* fin = (const char*)a.fin;
+    const uint32_t plane = (uint32_t)a.npad * SZ;
     double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int al = 0; al < 27; ++al) {
-        const double v = (double)Traits<S>::ld(fin, (uint32_t)al * np + (uint32_t)i);
+        const double v = (double)ldp<S>(fin, (uint32_t)al * plane + (uint32_t)i * SZ);
         d += v;
         jx += cxo(al) * v;
         jy += cyo(al) * v;
@@ -430,13 +618,14 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, double* rho, doub
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_read_pop(StepArgs a, double* out) {
+    constexpr uint32_t SZ = sizeof(S);
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= a.n) return;
-    const S* fin = (const S*)a.fin;
-    const uint32_t np = (uint32_t)a.npad;
+    const char* fin = (const char*)a.fin;
+    const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
     for (int al = 0; al < 27; ++al)
-        out[(size_t)al * a.n + i] = (double)Traits<S>::ld(fin, (uint32_t)al * np + (uint32_t)i);
+        out[(size_t)al * a.n + i] = (double)ldp<S>(fin, (uint32_t)al * plane + (uint32_t)i * SZ);
 }
 
 // Fixed-order reduction of the per-block monitor partials (one work-group).
@@ -467,31 +656,24 @@ __global__ void k_fill_zero(uint32_t* p, size_t nwords) {
         p[k] = 0u;
 }
 
-template <class S>
-hipError_t step_t(const StepArgs& a, bool full, hipStream_t st) {
+template <class S, bool MON, bool ONE>
+hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
     const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
-    if (full) hipLaunchKernelGGL((k_step<S, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_step<S, false>), grid, block, 0, st, a);
+    if (per) hipLaunchKernelGGL((k_step<S, MON, ONE, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_step<S, MON, ONE, false>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
-}  // namespace
-
-// Storage codes follow lbm.h: 0 F64, 1 F32, 2 F16S, 3 BF16S.
-#define LBM_DISPATCH(storage, FN, ...)                                  \
-    switch (storage) {                                                  \
-        case 0: return FN<double>(__VA_ARGS__);                         \
-        case 1: return FN<float>(__VA_ARGS__);                          \
-        case 2: return FN<_Float16>(__VA_ARGS__);                       \
-        case 3: return FN<__bf16>(__VA_ARGS__);                         \
-        default: return hipErrorInvalidValue;                           \
+template <class S>
+hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.monitor) {
+        return v.rates_one ? step_per<S, true, true>(a, v.periodic_yz, st)
+                           : step_per<S, true, false>(a, v.periodic_yz, st);
     }
-
-hipError_t launch_step(int storage, const StepArgs& a, bool full, hipStream_t stream) {
-    LBM_DISPATCH(storage, step_t, a, full, stream);
+    return v.rates_one ? step_per<S, false, true>(a, v.periodic_yz, st)
+                       : step_per<S, false, false>(a, v.periodic_yz, st);
 }
 
-namespace {
 template <class S>
 hipError_t init_t(const StepArgs& a, const double* rho, const double* u, hipStream_t st) {
     hipLaunchKernelGGL((k_init<S>), dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, a, rho, u);
@@ -509,7 +691,22 @@ hipError_t readpop_t(const StepArgs& a, double* out, hipStream_t st) {
     hipLaunchKernelGGL((k_read_pop<S>), dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, a, out);
     return hipGetLastError();
 }
+
 }  // namespace
+
+// Storage codes follow lbm.h: 0 F64, 1 F32, 2 F16S, 3 BF16S.
+#define LBM_DISPATCH(storage, FN, ...)                                  \
+    switch (storage) {                                                  \
+        case 0: return FN<double>(__VA_ARGS__);                         \
+        case 1: return FN<float>(__VA_ARGS__);                          \
+        case 2: return FN<_Float16>(__VA_ARGS__);                       \
+        case 3: return FN<__bf16>(__VA_ARGS__);                         \
+        default: return hipErrorInvalidValue;                           \
+    }
+
+hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream) {
+    LBM_DISPATCH(storage, step_t, a, v, stream);
+}
 
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream) {

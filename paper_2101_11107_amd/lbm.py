@@ -232,7 +232,9 @@ class Domain:
             raise RuntimeError("a GPU is required (the library has no CPU path)")
         self.torch = torch
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # A dedicated stream (default priority): work on it can be captured into
+        # graphs, which the default stream does not allow.
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.case = case
         self.handle = lbm_create_domain(case.mask, case.periodic, self.storage, self.stream.cuda_stream)
@@ -241,6 +243,8 @@ class Domain:
         self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.mem.data_ptr()) % 256
         self.view = self.mem[off: off + nbytes]
+        self.mem.record_stream(self.stream)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         lbm_attach_device(self.handle, self.view)
         lbm_set_params(self.handle, case.tau, case.rates, case.g)
         if case.inlet is not None:
@@ -248,7 +252,16 @@ class Domain:
             lbm_set_inlet_womersley(self.handle, i.axis, i.center, i.radius, i.G0, i.G1, i.omega)
         lbm_set_outlet_pressure(self.handle, case.rho_out)
 
+    def _in(self):
+        # work queued on torch's stream (allocations, inputs) precedes ours
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _out(self):
+        # results are consumed on torch's stream
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def init(self, rho=None, u=None):
+        self._in()
         lbm_init_equilibrium(self.handle, rho, u)
 
     def step(self, n):
@@ -261,14 +274,35 @@ class Domain:
         t = self.torch
         rho = t.empty(self.n, dtype=t.float64, device=self.device)
         u = t.empty((3, self.n), dtype=t.float64, device=self.device)
+        self._in()
         lbm_moments(self.handle, rho, u)
+        self._out()
         return rho, u
 
     def populations(self):
         t = self.torch
         f = t.empty((27, self.n), dtype=t.float64, device=self.device)
+        self._in()
         lbm_read_populations(self.handle, f)
+        self._out()
         return f
+
+    def average(self, op):
+        """op: LBM_AVG_RESET / LBM_AVG_ACCUMULATE, or LBM_AVG_READ (returns [3, n])."""
+        out = None
+        if op == LBM_AVG_READ:
+            out = self.torch.empty((3, self.n), dtype=self.torch.float64, device=self.device)
+            self._in()
+        lbm_average(self.handle, op, out)
+        if out is not None:
+            self._out()
+        return out
+
+    def get_state(self):
+        return lbm_get_state(self.handle)
+
+    def set_state(self, blob):
+        lbm_set_state(self.handle, blob)
 
     def monitors(self):
         return lbm_monitors(self.handle)
