@@ -87,7 +87,9 @@ const char* lbm_last_error(void);
  * INLET ghost by the velocity inlet rule and from an OUTLET ghost by the
  * pressure outlet rule.  periodic_bits: LBM_PERIODIC_* flags.  storage:
  * LBM_F64 / F32 / F16S / BF16S.  hip_stream: hipStream_t (NULL = default).
- * Fluid nodes are numbered in x-fastest order (x, then y, then z).
+ * Fluid nodes are numbered row by row, x fastest within a row; the (y, z)
+ * rows are taken in tiles of 8 x 8 (tile y fastest, then tile z, and y
+ * fastest inside a tile).  lbm_fluid_coords gives the order explicitly.
  * Errors: EINVAL for bad sizes, values or flags; ENOMEM on host allocation. */
 int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
                       int storage, void* hip_stream, lbm_domain** out);

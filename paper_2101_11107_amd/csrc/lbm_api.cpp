@@ -11,12 +11,16 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "lbm.h"
 #include "lbm_internal.h"
 
 using lbm::SpecialNode;
 
 namespace {
+
+constexpr int ROW_TILE = 8;   // rows per tile side in the list order
 
 thread_local std::string g_last_error;
 
@@ -283,12 +287,16 @@ int prepare_links(lbm_domain* d) {
 }
 
 constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffer parity
+// Population working sets above this size do not stay in the 256 MB Infinity
+// Cache; there streaming (non-temporal) stores are faster.
+constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
 
 // Launch nsteps steps; the last one accumulates the monitors.
 int launch_steps_eager(lbm_domain* d, int nsteps) {
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
-        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz()};
+        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(),
+                                 2 * d->pop_bytes > STREAM_STORE_BYTES};
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
         d->cur ^= 1;
     }
@@ -378,11 +386,23 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                 for (int x = 0; x < nx; ++x)
                     if (mask[d->cell(x, y, z)] == LBM_FLUID) d->rowtab[r + ((x + 1) >> 5)].bits |= 1u << ((x + 1) & 31);
             }
+        // List order: rows grouped in tiles of ROW_TILE x ROW_TILE rows of the
+        // (y, z) plane, x fastest inside a row.  Neighbouring rows then sit close
+        // together in the list, so the lines a wave gathers from are shared by
+        // waves that run at nearly the same time.
+        std::vector<int> order;
+        order.reserve((size_t)ny * nz);
+        for (int tz = 0; tz < nz; tz += ROW_TILE)
+            for (int ty = 0; ty < ny; ty += ROW_TILE)
+                for (int z = tz; z < std::min(nz, tz + ROW_TILE); ++z)
+                    for (int y = ty; y < std::min(ny, ty + ROW_TILE); ++y) order.push_back(d->row_of(y, z));
         int64_t cnt = 0;
-        for (auto& e : d->rowtab) {
-            e.prefix = (int32_t)cnt;
-            cnt += __builtin_popcount(e.bits);
-        }
+        for (int r : order)
+            for (int wd = 0; wd < d->W; ++wd) {
+                lbm::RowEntry& e = d->rowtab[(size_t)r * d->W + wd];
+                e.prefix = (int32_t)cnt;
+                cnt += __builtin_popcount(e.bits);
+            }
         if (cnt != nfluid) return fail(LBM_EINVAL, "internal: bitmap count mismatch");
         if ((int64_t)d->rows * d->W >= ((int64_t)1 << 29)) return fail(LBM_EINVAL, "box too large for the row table");
 
@@ -392,9 +412,9 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
         const bool per[3] = {(periodic_bits & 1) != 0, (periodic_bits & 2) != 0, (periodic_bits & 4) != 0};
         const bool per_yz = per[1] || per[2];
         int64_t i = 0;
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
+        for (int r : order) {
+            const int z = r / (ny + 2) - 1, y = r % (ny + 2) - 1;
+            for (int x = 0; x < nx; ++x) {
                     if (mask[d->cell(x, y, z)] != LBM_FLUID) continue;
                     d->coords[3 * i] = x;
                     d->coords[3 * i + 1] = y;
@@ -459,7 +479,8 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                         d->node_words[i] = lbm::SPECIAL_BIT | (uint32_t)sidx;
                     }
                     ++i;
-                }
+            }
+        }
 
         // device layout
         const size_t sb = storage_bytes(storage);

@@ -78,6 +78,7 @@ struct StepVariant {
     bool monitor;        // accumulate the FP64 monitors (mass, momentum, wall force, fluxes)
     bool rates_one;      // free rates of orders 3..6 all equal to 1
     bool periodic_yz;    // a periodic y or z axis (node words hold x, y, z)
+    bool stream_store;   // non-temporal population stores (working set beyond the Infinity Cache)
 };
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.

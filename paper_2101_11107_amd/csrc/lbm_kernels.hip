@@ -60,9 +60,10 @@ template <class S>
 __device__ __forceinline__ typename Traits<S>::T ldp(const char* __restrict__ base, uint32_t off) {
     return Traits<S>::cvt(*(const S*)(base + off));
 }
-template <class S>
+template <class S, bool NT = false>
 __device__ __forceinline__ void stp(char* __restrict__ base, uint32_t off, typename Traits<S>::T v) {
-    *(S*)(base + off) = Traits<S>::store(v);
+    if (NT) __builtin_nontemporal_store(Traits<S>::store(v), (S*)(base + off));   // streaming store
+    else *(S*)(base + off) = Traits<S>::store(v);
 }
 
 // Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
@@ -264,6 +265,9 @@ struct __attribute__((aligned(8))) RowPair {
 };
 
 // Ordinary node: streaming and halfway bounce-back through the row table.
+// The nine row-table entries are loaded first and the population loads issued
+// after all of them (vector loads retire in order, so interleaving them would
+// serialize the rows).
 template <class S, bool PER, bool WALLS>
 __device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const StepArgs& a, int i,
                                             uint32_t w, typename Traits<S>::T (&f)[27],
@@ -284,38 +288,42 @@ __device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const 
     const uint32_t sh = (uint32_t)x & 31u;
     const uint32_t low = (uint32_t)((2ull << sh) - 1ull);
     const int rowlen = a.ny + 2;
+    RowPair rp[9];
 #pragma unroll
-    for (int kz = 0; kz < 3; ++kz) {
+    for (int q = 0; q < 9; ++q) {
+        const int ky = q % 3, kz = q / 3;
+        uint32_t e;
+        if (!PER) {
+            e = e0 - (uint32_t)(((ky - 1) + (kz - 1) * rowlen) * a.W);
+        } else {
+            int ys = y - (ky - 1), zs = z - (kz - 1);
+            if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
+            if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
+            e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
+        }
+        rp[q] = *(const RowPair*)(rt + e * 8u);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            uint32_t e;
-            if (!PER) {
-                e = e0 - (uint32_t)(((ky - 1) + (kz - 1) * rowlen) * a.W);
-            } else {
-                int ys = y - (ky - 1), zs = z - (kz - 1);
-                if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
-                if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
-                e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
+    for (int q = 0; q < 9; ++q) {
+        const int ky = q % 3, kz = q / 3;
+        // bits of cells x - 1, x, x + 1 of this row
+        const uint32_t win = __builtin_amdgcn_alignbit(rp[q].w1, rp[q].w0, sh);
+        const int base = (q == 4) ? i : rp[q].p0 + (int)__popc(rp[q].w0 & low);
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int al = 9 * kz + 3 * ky + kx;
+            const int k = 2 - kx;              // bit of the source cell x - cx
+            if (al == 13) {
+                f[al] = ldp<S>(fin, 13u * plane + ib);
+                continue;
             }
-            const RowPair rp = *(const RowPair*)(rt + e * 8u);
-            // bits of cells x - 1, x, x + 1 of this row
-            const uint32_t win = __builtin_amdgcn_alignbit(rp.w1, rp.w0, sh);
-            const int base = (ky == 1 && kz == 1) ? i : rp.p0 + (int)__popc(rp.w0 & low);
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int al = 9 * kz + 3 * ky + kx;
-                const int k = 2 - kx;              // bit of the source cell x - cx
-                if (al == 13) {
-                    f[al] = ldp<S>(fin, 13u * plane + ib);
-                    continue;
-                }
-                const bool fl = (win >> k) & 1u;
-                const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
-                const uint32_t off = fl ? (uint32_t)al * plane + (uint32_t)src * SZ
-                                        : (uint32_t)(26 - al) * plane + ib;
-                f[al] = ldp<S>(fin, off);
-                if (WALLS && !fl) wallmask |= 1u << al;
-            }
+            const bool fl = (win >> k) & 1u;
+            const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
+            const uint32_t off = fl ? (uint32_t)al * plane + (uint32_t)src * SZ
+                                    : (uint32_t)(26 - al) * plane + ib;
+            f[al] = ldp<S>(fin, off);
+            if (WALLS && !fl) wallmask |= 1u << al;
         }
     }
 }
@@ -469,7 +477,7 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
 }
 
 // --- the step kernel ----------------------------------------------------------------
-template <class S, bool MON, bool ONE, bool PER>
+template <class S, bool MON, bool ONE, bool PER, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
         const uint32_t plane = (uint32_t)a.npad * SZ;
         const uint32_t ib = (uint32_t)i * SZ;
 #pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S>(fout, (uint32_t)al * plane + ib, f[al]);
+        for (int al = 0; al < 27; ++al) stp<S, NT>(fout, (uint32_t)al * plane + ib, f[al]);
         // after the stores, so the populations are no longer live
         if (sp != nullptr && sp->linkmask != 0u)
             update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);
@@ -552,8 +560,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
     const double r = rho0 ? rho0[i] : 1.0;
     const double u[3] = {u0 ? u0[i] : 0.0, u0 ? u0[a.n + i] : 0.0, u0 ? u0[2 * a.n + i] : 0.0};
     T f[27];
+    // the rest state is exactly zero in shifted variables
 #pragma unroll
-    for (int al = 0; al < 27; ++al) f[al] = (T)(feq1(al, r, u) - wgt(al));
+    for (int al = 0; al < 27; ++al) f[al] = (rho0 || u0) ? (T)(feq1(al, r, u) - wgt(al)) : T(0);
     T ux, uy, uz, drho, jx, jy, jz;
     if (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0)
         collide<T, true>(f, a, ux, uy, uz, drho, jx, jy, jz);
@@ -656,22 +665,32 @@ __global__ void k_fill_zero(uint32_t* p, size_t nwords) {
         p[k] = 0u;
 }
 
-template <class S, bool MON, bool ONE>
+template <class S, bool MON, bool ONE, bool NT>
 hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
     const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
-    if (per) hipLaunchKernelGGL((k_step<S, MON, ONE, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_step<S, MON, ONE, false>), grid, block, 0, st, a);
+    if (per) hipLaunchKernelGGL((k_step<S, MON, ONE, true, NT>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_step<S, MON, ONE, false, NT>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
+template <class S, bool NT>
+hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.monitor) {
+        return v.rates_one ? step_per<S, true, true, NT>(a, v.periodic_yz, st)
+                           : step_per<S, true, false, NT>(a, v.periodic_yz, st);
+    }
+    return v.rates_one ? step_per<S, false, true, NT>(a, v.periodic_yz, st)
+                       : step_per<S, false, false, NT>(a, v.periodic_yz, st);
+}
+
+// Streaming stores only pay for 4- and 8-byte populations (measured); the
+// 2-byte forms always store normally.
 template <class S>
 hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if (v.monitor) {
-        return v.rates_one ? step_per<S, true, true>(a, v.periodic_yz, st)
-                           : step_per<S, true, false>(a, v.periodic_yz, st);
+    if constexpr (sizeof(S) >= 4) {
+        if (v.stream_store) return step_nt<S, true>(a, v, st);
     }
-    return v.rates_one ? step_per<S, false, true>(a, v.periodic_yz, st)
-                       : step_per<S, false, false>(a, v.periodic_yz, st);
+    return step_nt<S, false>(a, v, st);
 }
 
 template <class S>

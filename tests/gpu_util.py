@@ -7,8 +7,16 @@ W = np.array([(1 / 6 if cx else 2 / 3) * (1 / 6 if cy else 2 / 3) * (1 / 6 if cz
 C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)], np.float64)
 
 
+def oracle_order(coords, mask):
+    """Permutation taking library node order to the oracle's x-fastest order."""
+    nz, ny, nx = mask.shape
+    key = (coords[:, 2].astype(np.int64) * ny + coords[:, 1]) * nx + coords[:, 0]
+    return np.argsort(key, kind="stable")
+
+
 def gpu_run(case, storage, steps, device="cuda:0"):
-    """Run the HIP path; return (domain, shifted post-collision populations [n, 27] as FP64)."""
+    """Run the HIP path; return (domain, shifted post-collision populations [n, 27]
+    as FP64, in the oracle's x-fastest node order)."""
     import torch
     from paper_2101_11107_amd import lbm
     dom = lbm.Domain(case, storage=storage, device=device)
@@ -17,7 +25,8 @@ def gpu_run(case, storage, steps, device="cuda:0"):
         dom.step(steps)
     f = dom.populations().cpu().numpy().T.copy()
     torch.cuda.synchronize()
-    return dom, f
+    perm = oracle_order(dom.coords(), case.mask)
+    return dom, f[perm]
 
 
 def oracle_post(case, steps, nthreads=16):
