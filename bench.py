@@ -37,12 +37,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(storage, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; None otherwise."""
+def read_profile(storage, workload):
+    """Values of the committed rocprofv3 summary for this kernel and workload,
+    if it was taken on the current kernel source; {} otherwise."""
     path = os.path.join(ROOT, "profiles", f"traffic_{STEP_KERNEL}_{storage}_{workload}.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as fh:
         for line in fh:
@@ -50,9 +50,14 @@ def read_traffic(storage, workload):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
+        return {}
+    return vals
+
+
+def read_traffic(storage, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) or None."""
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(read_profile(storage, workload)["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -170,6 +175,11 @@ def main():
                    "steps_per_graph": 16},
         "roofline": roofline(main_run["n"], main_run["ms_per_step"], args.storage, traffic),
     }
+    prof = read_profile(args.storage, workload)
+    if prof.get("avg_step_kernel_us"):
+        # kernel-only average of the committed rocprofv3 trace (the event figure
+        # above also contains the short gaps between graph-launched kernels)
+        line["roofline"]["rocprof_avg_step_kernel_us"] = float(prof["avg_step_kernel_us"])
     mon = main_run["monitors"]
     line["monitors_last_step"] = {"mass": mon[0], "inlet_flux": mon[7], "outlet_flux": mon[8], "t": mon[9]}
 
