@@ -88,6 +88,50 @@ def run_form(torch, lbm, case, storage, warmup, steps, want_u=False):
     return out
 
 
+def batch_bench(torch, lbm, steps, storage="f16s"):
+    """48 uneven synthetic geometries (boxes 64^3..192^3, 5-12 % fluid, tau in
+    [0.51, 1]) stepped together by the autotuned batch against the same domains
+    stepped one after another (each with its own graph replays)."""
+    import synth
+    cases = synth.batch_cases()
+    doms = [lbm.Domain(c, storage=storage) for c in cases]
+    for d in doms:
+        d.init()
+    total = sum(d.n for d in doms)
+    b = lbm.Batch(doms)
+    tuned_ms = b.autotune(trial_steps=32, want_time=True)
+    cfg = b.config()
+    b.step(32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.status()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for d in doms:
+        d.step(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in doms:
+        d.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    b.close()
+    for d in doms:
+        d.close()
+    del doms
+    torch.cuda.empty_cache()
+    ms = t_batch * 1e3 / steps
+    return {"workload": "batch48_uneven", "storage": storage, "domains": len(cases), "fluid_nodes": total,
+            "steps": steps, "batched_mlups": round(total * steps / t_batch / 1e6, 1),
+            "sequential_mlups": round(total * steps / t_seq / 1e6, 1),
+            "batched_over_sequential": round(t_seq / t_batch, 3),
+            "autotuned_config": {"mode": ["launch_per_step", "persistent"][cfg[0]], "block": cfg[1],
+                                 "stream_store": cfg[2], "grid": cfg[3], "group_mb": cfg[4]},
+            "autotune_best_ms_per_step": round(tuned_ms, 4),
+            "roofline_frac": roofline(total, ms, storage, None)["frac"]}
+
+
 def roofline(n, ms_per_step, storage, traffic):
     alg = 54 * POP_BYTES[storage] * n                 # algorithmic bytes per launch
     achieved = alg / (ms_per_step * 1e-3) / 1e9
@@ -203,6 +247,7 @@ def main():
             also.append({"workload": "aneurysm512", "storage": st, "fluid_nodes": r["n"],
                          "mlups": round(r["mlups"], 1), "achieved_GBs": rf["achieved"],
                          "roofline_frac": rf["frac"], "traffic": rf["traffic"], "steps": steps_x})
+        also.append(batch_bench(torch, lbm, 480))
         line["also"] = also
 
     if not args.no_cpu_baseline:

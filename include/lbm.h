@@ -191,6 +191,55 @@ int lbm_inlet_profile(double r, double t, double radius, double nu, double G0, d
 /* Free the host side of the domain (the caller frees the device memory). */
 void lbm_destroy(lbm_domain* dom);
 
+/* ---- Batched stepping -----------------------------------------------------
+ * Many domains (uneven geometries, different tau) advanced by launches that
+ * cover all of them, so small domains fill the device together.  The domains
+ * keep their own memory, parameters and state; a batch step performs exactly
+ * the per-node arithmetic of lbm_step, so every domain ends bit-identical to
+ * stepping it alone.  All domains need the same storage type.  Batch work runs
+ * on the batch's stream: the caller orders it against the domains' streams
+ * (lbm_batch_step synchronizes each domain's stream before it enqueues). */
+
+/* Create a batch of n >= 1 distinct attached domains (the pointer array is
+ * copied; the domains must outlive the batch).  hip_stream: hipStream_t of
+ * the batch work (must not be the NULL stream for graph capture). */
+int lbm_batch_create(lbm_domain* const* doms, int n, void* hip_stream, lbm_batch** out);
+int lbm_batch_device_bytes(const lbm_batch* batch, size_t* bytes);
+/* Attach caller-owned device memory for the batch tables (256-byte aligned). */
+int lbm_batch_attach_device(lbm_batch* batch, void* dev_ptr, size_t bytes);
+
+/* Execution choice: cfg = { mode (0: one launch per step over the domains of
+ * a group; 1: persistent launch looping over the group's work with a
+ * device-wide barrier between steps), work-group size (128, 256 or 512),
+ * streaming stores (0/1; 4- and 8-byte storage only), persistent grid (0 =
+ * every work-group that fits at once), group budget in MiB (0: all domains
+ * form one group; otherwise consecutive domains are grouped while their
+ * population working set stays within the budget, and each group runs all
+ * requested steps before the next, which keeps it in the device cache) }.
+ * EINVAL for other values. */
+int lbm_batch_config(const lbm_batch* batch, int cfg[5]);
+int lbm_batch_set_config(lbm_batch* batch, const int cfg[5]);
+
+/* Autotuner: time every configuration on this batch for about trial_steps
+ * steps each (the domains advance by those steps) and keep the fastest;
+ * results are cached per process by storage, collision form, batch size
+ * class and domain count.  best_ms_per_step (nullable) receives the best
+ * time per step; when it is non-NULL the trials run even on a cache hit. */
+int lbm_batch_autotune(lbm_batch* batch, int trial_steps, double* best_ms_per_step);
+
+/* Advance every domain by nsteps (asynchronous on the batch stream; replays
+ * captured graphs of 16 steps).  The last step writes every domain's
+ * monitors (read them with lbm_monitors).  ESTATE unless every domain is
+ * initialised. */
+int lbm_batch_step(lbm_batch* batch, int nsteps);
+
+/* Synchronize the batch stream; EDEVICE if a persistent launch hit the bound
+ * of a device-wide barrier wait (its results are then invalid). */
+int lbm_batch_status(lbm_batch* batch);
+
+/* Free the host side of the batch (not the domains). */
+void lbm_batch_destroy(lbm_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,13 +14,12 @@
 #include <algorithm>
 
 #include "lbm.h"
+#include "lbm_host.h"
 #include "lbm_internal.h"
 
 using lbm::SpecialNode;
 
-namespace {
-
-constexpr int ROW_TILE = 8;   // rows per tile side in the list order
+namespace lbm_host {
 
 thread_local std::string g_last_error;
 
@@ -33,11 +32,13 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                          \
-    do {                                             \
-        hipError_t _e = (expr);                      \
-        if (_e != hipSuccess) return hip_fail(_e, what); \
-    } while (0)
+}  // namespace lbm_host
+
+using namespace lbm_host;
+
+namespace {
+
+constexpr int ROW_TILE = 8;   // rows per tile side in the list order
 
 size_t storage_bytes(int storage) {
     switch (storage) {
@@ -80,86 +81,20 @@ void womersley_coeffs(double r, double R, double nu, double G0, double G1, doubl
     }
 }
 
+}  // namespace
+
+namespace lbm_host {
+
 bool finite_all(const double* v, int n) {
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(v[i])) return false;
     return true;
 }
 
-}  // namespace
+}  // namespace lbm_host
 
-struct lbm_domain {
-    int nx = 0, ny = 0, nz = 0;
-    unsigned periodic = 0;
-    int storage = 0;
-    hipStream_t stream = nullptr;
 
-    int64_t n = 0;
-    int npad = 0;
-    int W = 0;
-    int rows = 0;
-    int nblocks = 0, blocks_per_xcd = 0;
-    std::vector<uint32_t> node_words;      // [npad]
-    std::vector<lbm::RowEntry> rowtab;     // [rows][W]
-    std::vector<SpecialNode> spec;
-    std::vector<int32_t> spec_plane;       // [nspec][27] plane of each pulled value
-    std::vector<int32_t> link_meta;        // [nlinks] type | alpha << 8
-    std::vector<double> link_coef;         // [nlinks][LINK_COEFS]
-    std::vector<int32_t> link_xyz;         // [nlinks][3] node coordinates of each link
-    std::vector<int32_t> coords;           // [n][3]
-    bool has_inlet_links = false;
-    size_t nlinks() const { return link_meta.size(); }
-
-    // parameters
-    bool params_set = false;
-    double tau = 0.0, s[4] = {1, 1, 1, 1}, g[3] = {0, 0, 0};
-    double rho_out = 1.0;
-    bool inlet_set = false;
-    double axis[3] = {0, 0, 1}, center[3] = {0, 0, 0}, radius = 0, G0 = 0, G1 = 0, omega = 0;
-    bool links_dirty = true;
-
-    // device memory
-    char* dev = nullptr;
-    size_t dev_bytes = 0;
-    size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
-           off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0;
-    size_t pop_bytes = 0;
-
-    int cur = 0;
-    int64_t t = 0;
-    int64_t t_upload[2] = {0, 0};
-    double trig_host[4] = {1, 0, 1, 0};   // (cos, sin)(omega t) for slots t & 1
-    bool initialized = false;
-    bool monitored = false;   // a monitored step ran since initialisation
-    int64_t avg_count = 0;
-    double mon_host[lbm::MON_WORDS] = {0};
-
-    // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer
-    // parity.  Kernel arguments are baked in, so any parameter change drops them.
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-
-    void drop_graphs() {
-        for (auto& g : graph) {
-            if (g) hipGraphExecDestroy(g);
-            g = nullptr;
-        }
-    }
-    ~lbm_domain() { drop_graphs(); }
-
-    int64_t cell(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
-    int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
-    // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
-    int32_t index_of(int x, int y, int z) const {
-        const int p = x + 1;
-        const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + (p >> 5)];
-        const uint32_t low = (p & 31) ? ((1u << (p & 31)) - 1u) : 0u;
-        return e.prefix + __builtin_popcount(e.bits & low);
-    }
-    bool rates_one() const { return s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0; }
-    bool periodic_yz() const { return (periodic & 6u) != 0; }
-};
-
-namespace {
+namespace lbm_host {
 
 lbm::StepArgs make_args(const lbm_domain* d) {
     lbm::StepArgs a{};
@@ -196,6 +131,10 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.rho_out = d->rho_out;
     return a;
 }
+
+}  // namespace lbm_host
+
+namespace {
 
 // Exact odd polynomial of the moving-wall term f_eq_a(1, axis U) - f_eq_abar(1, axis U)
 // in the speed U: the product form of the equilibrium is prod_d psi(c_d, axis_d U)
@@ -234,6 +173,10 @@ int upload_phase(lbm_domain* d, int64_t t) {
             "upload of the inlet phase");
     return LBM_OK;
 }
+
+}  // namespace
+
+namespace lbm_host {
 
 // Recompute the inlet coefficients (they depend on tau through nu) and upload
 // them with the inlet phase of the current time.
@@ -286,17 +229,16 @@ int prepare_links(lbm_domain* d) {
     return LBM_OK;
 }
 
-constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffer parity
-// Population working sets above this size do not stay in the 256 MB Infinity
-// Cache; there streaming (non-temporal) stores are faster.
-constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
+}  // namespace lbm_host
+
+namespace {
 
 // Launch nsteps steps; the last one accumulates the monitors.
 int launch_steps_eager(lbm_domain* d, int nsteps) {
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
         const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(),
-                                 2 * d->pop_bytes > STREAM_STORE_BYTES};
+                                 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES};
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
         d->cur ^= 1;
     }
@@ -509,7 +451,8 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
         d->off_ladd = take(nl * sizeof(double));
         d->off_tcount = take(2 * sizeof(int64_t));
         d->off_trig = take(4 * sizeof(double));
-        d->off_part = take((size_t)d->nblocks * lbm::MON_WORDS * sizeof(double));
+        // monitor partials: one per work-group, for work-groups down to 64 nodes
+        d->off_part = take((size_t)(npad / 64 + 1) * lbm::MON_WORDS * sizeof(double));
         d->off_monout = take(lbm::MON_WORDS * sizeof(double));
         d->off_avg = take((size_t)3 * nfluid * sizeof(double));
         d->dev_bytes = off;
@@ -654,7 +597,10 @@ int lbm_step(lbm_domain* d, int nsteps) {
     rc = launch_steps_eager(d, left);
     if (rc) return rc;
     d->t += nsteps;
-    if (nsteps > 0) d->monitored = true;
+    if (nsteps > 0) {
+        d->monitored = true;
+        d->mon_blocks = d->nblocks;
+    }
     return LBM_OK;
 }
 
@@ -703,7 +649,7 @@ int lbm_monitors(lbm_domain* d, double out[10]) {
     if (!d || !out) return fail(LBM_EINVAL, "NULL argument");
     if (!d->monitored) return fail(LBM_ESTATE, "no step has run since initialisation");
     double* mo = (double*)(d->dev + d->off_monout);
-    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->nblocks, mo, d->stream),
+    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->mon_blocks, mo, d->stream),
             "monitor reduction");
     HIP_TRY(hipMemcpyAsync(d->mon_host, mo, 9 * sizeof(double), hipMemcpyDeviceToHost, d->stream), "monitor copy");
     HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");

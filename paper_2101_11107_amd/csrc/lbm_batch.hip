@@ -1,0 +1,194 @@
+// Batched stepping of many domains (gfx950): every launch covers the blocks of
+// all domains of a batch, so small and uneven geometries fill the device
+// together instead of one after another.  Two forms:
+//  - k_batch_step: one launch per step (captured K at a time into a graph);
+//  - k_batch_persistent: one launch for K steps; the work-groups loop over the
+//    work items and meet at a device-wide barrier between steps.
+// Both call the same per-block step as the single-domain kernel, so each
+// domain's populations are bit-identical to stepping it alone.
+#include "lbm_device.h"
+
+namespace lbm {
+namespace {
+
+// Bound of a barrier wait (iterations of a ~100-cycle sleep, about 0.2 s).
+constexpr unsigned SPIN_LIMIT = 1u << 21;
+
+template <class S, bool MON, bool ONE, bool NT, int BS>
+__device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int step) {
+    const int packed = b.item_map[item];
+    StepArgs a = b.doms[packed >> ITEM_DOMAIN_SHIFT];
+    if (step & 1) {
+        const void* t = a.fin;
+        a.fin = a.fout;
+        a.fout = const_cast<void*>(t);
+        a.tin ^= 1;
+    }
+    const int lb = packed & ITEM_BLOCK_MASK;
+    if (a.periodic & 6) step_block<S, MON, ONE, true, NT, BS>(a, lb);
+    else step_block<S, MON, ONE, false, NT, BS>(a, lb);
+}
+
+template <class S, bool MON, bool ONE, bool NT, int BS>
+__global__ __launch_bounds__(BS) void k_batch_step(BatchArgs b, int step) {
+    // XCD-aware order as in the single-domain kernel
+    const int hb = blockIdx.x;
+    const int item = (hb & 7) * b.items_per_xcd + (hb >> 3);
+    if (item >= b.nitems) return;
+    batch_item<S, MON, ONE, NT, BS>(b, item, step);
+}
+
+// Device-wide barrier (sense by generation count).  Returns false if the wait
+// exceeded its bound; then the error flag is set and every work-group leaves.
+__device__ bool grid_barrier(const BatchArgs& b) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        unsigned* count = b.barrier;
+        unsigned* gen = b.barrier + 1;
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();   // release this work-group's stores
+        const unsigned arrived = atomicAdd(count, 1u);
+        if (arrived == gridDim.x - 1) {
+            atomicExch(count, 0u);
+            __threadfence();
+            atomicAdd(gen, 1u);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > SPIN_LIMIT || __hip_atomic_load(b.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicExch(b.error, 1);
+                    good = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();   // acquire the other work-groups' stores
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// Steps step0 .. step0 + nsteps - 1 without monitors (the monitored last step
+// of a sequence is a k_batch_step launch).
+template <class S, bool ONE, bool NT, int BS>
+__global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs b, int step0, int nsteps) {
+    for (int s = 0; s < nsteps; ++s) {
+        for (int item = blockIdx.x; item < b.nitems; item += gridDim.x)
+            batch_item<S, false, ONE, NT, BS>(b, item, step0 + s);
+        if (s + 1 < nsteps && !grid_barrier(b)) return;
+    }
+}
+
+template <class S, bool ONE, bool NT, int BS>
+hipError_t step_bs(const BatchArgs& b, int step, bool monitor, hipStream_t st) {
+    const dim3 grid(8 * b.items_per_xcd), block(BS);
+    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS>), grid, block, 0, st, b, step);
+    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS>), grid, block, 0, st, b, step);
+    return hipGetLastError();
+}
+
+template <class S, bool ONE, bool NT, int BS>
+hipError_t persistent_bs(const BatchArgs& b, int grid, int step0, int nsteps, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch_persistent<S, ONE, NT, BS>), dim3(grid), dim3(BS), 0, st, b, step0, nsteps);
+    return hipGetLastError();
+}
+
+template <class S, bool ONE, bool NT, int BS>
+hipError_t capacity_bs(int* blocks) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<S, ONE, NT, BS>, BS, 0);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
+}
+
+// Dispatch over (rates_one, stream_store, block); F is called as F<S, ONE, NT, BS>().
+#define BATCH_BS(S, ONE, NT, F, ...)                                              \
+    switch (c.block) {                                                            \
+        case 128: return F<S, ONE, NT, 128>(__VA_ARGS__);                         \
+        case 256: return F<S, ONE, NT, 256>(__VA_ARGS__);                         \
+        case 512: return F<S, ONE, NT, 512>(__VA_ARGS__);                         \
+        default: return hipErrorInvalidValue;                                     \
+    }
+
+template <class S, bool ONE>
+hipError_t step_one(const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
+    if constexpr (sizeof(S) >= 4) {
+        if (c.stream_store) BATCH_BS(S, ONE, true, step_bs, b, step, monitor, st)
+    }
+    BATCH_BS(S, ONE, false, step_bs, b, step, monitor, st)
+}
+
+template <class S, bool ONE>
+hipError_t persistent_one(const BatchArgs& b, const BatchConfig& c, int grid, int step0, int nsteps, hipStream_t st) {
+    if constexpr (sizeof(S) >= 4) {
+        if (c.stream_store) BATCH_BS(S, ONE, true, persistent_bs, b, grid, step0, nsteps, st)
+    }
+    BATCH_BS(S, ONE, false, persistent_bs, b, grid, step0, nsteps, st)
+}
+
+template <class S, bool ONE>
+hipError_t capacity_one(const BatchConfig& c, int* blocks) {
+    if constexpr (sizeof(S) >= 4) {
+        if (c.stream_store) BATCH_BS(S, ONE, true, capacity_bs, blocks)
+    }
+    BATCH_BS(S, ONE, false, capacity_bs, blocks)
+}
+
+template <class S>
+hipError_t step_s(bool one, const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
+    return one ? step_one<S, true>(b, c, step, monitor, st) : step_one<S, false>(b, c, step, monitor, st);
+}
+
+template <class S>
+hipError_t capacity_s(bool one, const BatchConfig& c, int* blocks) {
+    return one ? capacity_one<S, true>(c, blocks) : capacity_one<S, false>(c, blocks);
+}
+
+template <class S>
+hipError_t persistent_s(bool one, const BatchArgs& b, const BatchConfig& c, int step0, int nsteps, hipStream_t st) {
+    int grid = c.grid;
+    int cap = 0;
+    hipError_t e = capacity_s<S>(one, c, &cap);
+    if (e != hipSuccess) return e;
+    // never more work-groups than fit at once: the barrier needs them all resident
+    if (grid <= 0 || grid > cap) grid = cap;
+    if (grid > b.nitems) grid = b.nitems;
+    return one ? persistent_one<S, true>(b, c, grid, step0, nsteps, st)
+               : persistent_one<S, false>(b, c, grid, step0, nsteps, st);
+}
+
+}  // namespace
+
+#define LBM_DISPATCH_S(storage, FN, ...)                                \
+    switch (storage) {                                                  \
+        case 0: return FN<double>(__VA_ARGS__);                         \
+        case 1: return FN<float>(__VA_ARGS__);                          \
+        case 2: return FN<_Float16>(__VA_ARGS__);                       \
+        case 3: return FN<__bf16>(__VA_ARGS__);                         \
+        default: return hipErrorInvalidValue;                           \
+    }
+
+hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+                             bool monitor, hipStream_t stream) {
+    LBM_DISPATCH_S(storage, step_s, rates_one, b, c, step, monitor, stream);
+}
+
+hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+                                   int step0, int nsteps, hipStream_t stream) {
+    LBM_DISPATCH_S(storage, persistent_s, rates_one, b, c, step0, nsteps, stream);
+}
+
+hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks) {
+    LBM_DISPATCH_S(storage, capacity_s, rates_one, c, blocks);
+}
+
+}  // namespace lbm

@@ -1,0 +1,115 @@
+// Host-side internals of the library shared by the domain API (lbm_api.cpp)
+// and the batch API (lbm_batch_api.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace lbm_host {
+
+// Error reporting: the message is kept per thread for lbm_last_error().
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+bool finite_all(const double* v, int n);
+
+constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffer parity
+// Population working sets above this size do not stay in the 256 MB Infinity
+// Cache; there streaming (non-temporal) stores are faster.
+constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
+
+}  // namespace lbm_host
+
+#define HIP_TRY(expr, what)                                            \
+    do {                                                               \
+        hipError_t _e = (expr);                                        \
+        if (_e != hipSuccess) return lbm_host::hip_fail(_e, what);     \
+    } while (0)
+
+// A domain: host tables, parameters, the layout of its device memory and its
+// time/buffer bookkeeping.
+struct lbm_domain {
+    int nx = 0, ny = 0, nz = 0;
+    unsigned periodic = 0;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+
+    int64_t n = 0;
+    int npad = 0;
+    int W = 0;
+    int rows = 0;
+    int nblocks = 0, blocks_per_xcd = 0;
+    std::vector<uint32_t> node_words;      // [npad]
+    std::vector<lbm::RowEntry> rowtab;     // [rows][W]
+    std::vector<lbm::SpecialNode> spec;
+    std::vector<int32_t> spec_plane;       // [nspec][27] plane of each pulled value
+    std::vector<int32_t> link_meta;        // [nlinks] type | alpha << 8
+    std::vector<double> link_coef;         // [nlinks][LINK_COEFS]
+    std::vector<int32_t> link_xyz;         // [nlinks][3] node coordinates of each link
+    std::vector<int32_t> coords;           // [n][3]
+    bool has_inlet_links = false;
+    size_t nlinks() const { return link_meta.size(); }
+
+    // parameters
+    bool params_set = false;
+    double tau = 0.0, s[4] = {1, 1, 1, 1}, g[3] = {0, 0, 0};
+    double rho_out = 1.0;
+    bool inlet_set = false;
+    double axis[3] = {0, 0, 1}, center[3] = {0, 0, 0}, radius = 0, G0 = 0, G1 = 0, omega = 0;
+    bool links_dirty = true;
+
+    // device memory
+    char* dev = nullptr;
+    size_t dev_bytes = 0;
+    size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
+           off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0;
+    size_t pop_bytes = 0;
+
+    int cur = 0;
+    int64_t t = 0;
+    int64_t t_upload[2] = {0, 0};
+    double trig_host[4] = {1, 0, 1, 0};   // (cos, sin)(omega t) for slots t & 1
+    bool initialized = false;
+    bool monitored = false;   // a monitored step ran since initialisation
+    int mon_blocks = 0;       // monitor partials written by that step
+    int64_t avg_count = 0;
+    double mon_host[lbm::MON_WORDS] = {0};
+
+    // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer
+    // parity.  Kernel arguments are baked in, so any parameter change drops them.
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+    void drop_graphs() {
+        for (auto& g : graph) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
+    ~lbm_domain() { drop_graphs(); }
+
+    int64_t cell(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
+    int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
+    // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
+    int32_t index_of(int x, int y, int z) const {
+        const int p = x + 1;
+        const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + (p >> 5)];
+        const uint32_t low = (p & 31) ? ((1u << (p & 31)) - 1u) : 0u;
+        return e.prefix + __builtin_popcount(e.bits & low);
+    }
+    bool rates_one() const { return s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0; }
+    bool periodic_yz() const { return (periodic & 6u) != 0; }
+};
+
+namespace lbm_host {
+
+// Kernel arguments for the domain's current buffer parity.
+lbm::StepArgs make_args(const lbm_domain* d);
+// Upload the open-boundary coefficients and inlet phase if they changed.
+int prepare_links(lbm_domain* d);
+
+}  // namespace lbm_host

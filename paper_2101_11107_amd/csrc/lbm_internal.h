@@ -81,6 +81,29 @@ struct StepVariant {
     bool stream_store;   // non-temporal population stores (working set beyond the Infinity Cache)
 };
 
+// Several domains stepped by one launch.  Work item k of the launch is block
+// (item_map[k] & ITEM_BLOCK_MASK) of domain (item_map[k] >> ITEM_DOMAIN_SHIFT);
+// doms[d] holds the domain's arguments for its buffer parity at the start of
+// the launch sequence (odd steps swap the buffers and the time slot).
+constexpr int ITEM_DOMAIN_SHIFT = 20;
+constexpr int ITEM_BLOCK_MASK = (1 << ITEM_DOMAIN_SHIFT) - 1;
+struct BatchArgs {
+    const StepArgs* doms;        // [ndom]
+    const int* item_map;         // [nitems]
+    int ndom, nitems, items_per_xcd;
+    unsigned* barrier;           // [2] arrival count and generation (persistent mode)
+    int* error;                  // set when a device-wide barrier wait exceeded its bound
+};
+
+// Execution choices of a batch (picked by the autotuner).
+struct BatchConfig {
+    int mode;            // 0: one launch per step; 1: persistent launch with device-wide barriers
+    int block;           // work-group size: 128, 256 or 512
+    int stream_store;    // non-temporal population stores
+    int grid;            // persistent mode: number of work-groups (0 = all that fit)
+    int group_mb;        // domains stepped together per group, by population working set (0 = all)
+};
+
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream);
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
@@ -91,5 +114,14 @@ hipError_t launch_read_populations(int storage, const StepArgs& a, double* out, 
 hipError_t launch_monitor_finalize(const double* partials, int nblocks, double* out,
                                    hipStream_t stream);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
+
+// Batched launchers (lbm_batch.hip).  step: the step index within the launch
+// sequence (its parity selects the buffers); monitor: accumulate monitors.
+hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+                             bool monitor, hipStream_t stream);
+hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+                                   int step0, int nsteps, hipStream_t stream);
+// Work-groups of the persistent kernel that fit on the device at once.
+hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks);
 
 }  // namespace lbm

@@ -1,548 +1,20 @@
-// HIP kernels of the D3Q27 CHM-MRT lattice Boltzmann step for gfx950 (MI355X).
-//
-// One fused pull-scheme kernel per time step (Eq. (1)): every work-item owns
-// one fluid node, gathers the 27 incoming post-collision populations of the
-// previous step from the structure-of-arrays buffer (halfway bounce-back for
-// wall links, Eq. (9) at q = 1/2; inlet/outlet rules for open links), forms
-// rho and j (Eqs. (4)-(5)), applies the central Hermite moment collision
-// (Eq. (6) with the equilibrium central moments (rho, 0, ..., 0) of Eq. (8)) in
-// registers with one-dimensional transforms along x, y and z, and stores the
-// 27 post-collision populations.  Populations are stored shifted by their
-// weights (f - w_alpha) and the collision works on deviations, so every
-// intermediate value is small and reduced-precision storage keeps its relative
-// accuracy.
-//
-// Addressing: a node's neighbours in row (y', z') are located through a row
-// table that holds, per 32 cells, the fluid bitmap word and the number of fluid
-// nodes before it in x-fastest order: the index of fluid cell (x', y', z') is
-// that count plus the popcount of the preceding bits.  Besides the populations
-// only one 4-byte descriptor per node is streamed; the row table is shared by a
-// wavefront and stays in cache.  Loads use 32-bit byte offsets from a uniform
-// base, so each population address costs one or two integer operations.
-#include "lbm_internal.h"
+// Single-domain HIP kernels of the lattice Boltzmann library (gfx950) and
+// their launchers: the step, initialisation, moments, population read-out,
+// monitor reduction and buffer clearing.
+#include "lbm_device.h"
 
 namespace lbm {
 namespace {
 
-// --- lattice ------------------------------------------------------------------
-// alpha = 9 (cz + 1) + 3 (cy + 1) + (cx + 1); opposite = 26 - alpha.
-__host__ __device__ constexpr int cxo(int a) { return a % 3 - 1; }
-__host__ __device__ constexpr int cyo(int a) { return (a / 3) % 3 - 1; }
-__host__ __device__ constexpr int czo(int a) { return a / 9 - 1; }
-__host__ __device__ constexpr double w1d(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
-__host__ __device__ constexpr double wgt(int a) { return w1d(cxo(a)) * w1d(cyo(a)) * w1d(czo(a)); }
-
-// --- storage traits -------------------------------------------------------------
-template <class S> struct Traits;
-template <> struct Traits<double> {
-    using T = double;
-    __device__ static T cvt(double v) { return v; }
-    __device__ static double store(T v) { return v; }
-};
-template <> struct Traits<float> {
-    using T = float;
-    __device__ static T cvt(float v) { return v; }
-    __device__ static float store(T v) { return v; }
-};
-template <> struct Traits<_Float16> {
-    using T = float;
-    __device__ static T cvt(_Float16 v) { return (float)v; }
-    __device__ static _Float16 store(T v) { return (_Float16)v; }    // round to nearest even
-};
-template <> struct Traits<__bf16> {
-    using T = float;
-    __device__ static T cvt(__bf16 v) { return (float)v; }
-    __device__ static __bf16 store(T v) { return (__bf16)v; }        // round to nearest even
-};
-
-// Load / store of one population at a byte offset from a uniform base.
-template <class S>
-__device__ __forceinline__ typename Traits<S>::T ldp(const char* __restrict__ base, uint32_t off) {
-    return Traits<S>::cvt(*(const S*)(base + off));
-}
-template <class S, bool NT = false>
-__device__ __forceinline__ void stp(char* __restrict__ base, uint32_t off, typename Traits<S>::T v) {
-    if (NT) __builtin_nontemporal_store(Traits<S>::store(v), (S*)(base + off));   // streaming store
-    else *(S*)(base + off) = Traits<S>::store(v);
-}
-
-// Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
-__device__ inline double feq1(int a, double rho, const double u[3]) {
-    double r = rho;
-    const int c[3] = {cxo(a), cyo(a), czo(a)};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double v = u[d];
-        r *= (c[d] == 0) ? (2.0 / 3.0 - v * v) : 0.5 * (1.0 / 3.0 + v * v + c[d] * v);
-    }
-    return r;
-}
-
-// --- central Hermite transforms on one line (c = -1, 0, +1) ---------------------
-// Forward: (f-, f0, f+) -> (m0, m1, m2) with H0 = 1, H1 = c - u, H2 = (c - u)^2 - 1/3.
-template <class T>
-__device__ __forceinline__ void fwd1(T& a, T& b, T& c, T u, T u2m) {
-    const T m0 = a + b + c;
-    const T d = c - a;
-    const T s = c + a;
-    a = m0;
-    b = d - u * m0;
-    c = s - T(2) * u * d + u2m * m0;          // u2m = u^2 - 1/3
-}
-// Inverse of fwd1.
-template <class T>
-__device__ __forceinline__ void inv1(T& a, T& b, T& c, T u, T u2p) {
-    const T r1 = b + u * a;
-    const T r2 = c + T(2) * u * b + u2p * a;  // u2p = u^2 + 1/3
-    const T m0 = a;
-    a = T(0.5) * (r2 - r1);
-    b = m0 - r2;
-    c = T(0.5) * (r2 + r1);
-}
-// Inverse with the first- and second-order inputs given at half scale
-// (b = m1/2, c = m2/2): k = r1/2, h = r2/2, f- = h - k, f0 = m0 - 2h, f+ = h + k.
-template <class T>
-__device__ __forceinline__ void inv1h(T& a, T& b, T& c, T uh, T u2, T u2ph) {
-    const T k = b + uh * a;                   // uh = u/2
-    const T h = c + u2 * b + u2ph * a;        // u2 = 2u, u2ph = (u^2 + 1/3)/2
-    const T m0 = a;
-    a = h - k;
-    b = m0 - T(2) * h;
-    c = h + k;
-}
-
-// Line sums over x for the nine (cy, cz) lines q = 3 (cz + 1) + (cy + 1).
-template <class T>
-__device__ __forceinline__ void line_sums(const T (&f)[27], T (&S0)[9], T (&S1)[9], T (&S2)[9]) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        S1[q] = f[3 * q + 2] - f[3 * q];
-        S2[q] = f[3 * q + 2] + f[3 * q];
-        S0[q] = S2[q] + f[3 * q + 1];
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void conserved(const T (&S0)[9], const T (&S1)[9], T& drho, T& jx, T& jy, T& jz) {
-    // rho - 1 and j of the shifted populations (sum w = 1, sum w c = 0)
-    const T zm = S0[0] + S0[1] + S0[2], z0 = S0[3] + S0[4] + S0[5], zp = S0[6] + S0[7] + S0[8];
-    const T ym = S0[0] + S0[3] + S0[6], yp = S0[2] + S0[5] + S0[8];
-    drho = (zm + z0) + zp;
-    jx = ((S1[0] + S1[1]) + (S1[2] + S1[3])) + ((S1[4] + S1[5]) + (S1[6] + S1[7])) + S1[8];
-    jy = yp - ym;
-    jz = zp - zm;
-}
-
-// General collision (any free rates), deviation form.  With dA = T(u) f_hat and
-// (T w)_ijk = p_i(ux) p_j(uy) p_k(uz), p = (1, -u, u^2), the post-collision
-// deviations are: order 0: d rho; order 1: rho g / 2 + u; order n >= 2:
-// (1 - s_n) dA - s_n (T w); then f_hat* = T(u)^-1 of them.
-template <class T>
-__device__ __forceinline__ void collide_general(T (&f)[27], T drho, T ux, T uy, T uz, T hr,
-                                                const T (&om)[5], const T (&sr)[5], const T (&g)[3]) {
-    const T third = T(1) / T(3);
-    const T xm = ux * ux - third, ym = uy * uy - third, zm = uz * uz - third;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fwd1(f[3 * q], f[3 * q + 1], f[3 * q + 2], ux, xm);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) fwd1(f[9 * k + i], f[9 * k + i + 3], f[9 * k + i + 6], uy, ym);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fwd1(f[q], f[q + 9], f[q + 18], uz, zm);
-
-    const T px[3] = {T(1), -ux, ux * ux};
-    const T py[3] = {T(1), -uy, uy * uy};
-    const T pz[3] = {T(1), -uz, uz * uz};
-#pragma unroll
-    for (int m = 0; m < 27; ++m) {
-        const int i = m % 3, j = (m / 3) % 3, k = m / 9, n = i + j + k;
-        if (n == 0) {
-            f[m] = drho;
-        } else if (n == 1) {
-            f[m] = (i == 1) ? hr * g[0] + ux : ((j == 1) ? hr * g[1] + uy : hr * g[2] + uz);
-        } else {
-            const T tw = px[i] * py[j] * pz[k];
-            f[m] = om[n - 2] * f[m] - sr[n - 2] * tw;
-        }
-    }
-
-    const T xp = ux * ux + third, yp = uy * uy + third, zp = uz * uz + third;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) inv1(f[q], f[q + 9], f[q + 18], uz, zp);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) inv1(f[9 * k + i], f[9 * k + i + 3], f[9 * k + i + 6], uy, yp);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) inv1(f[3 * q], f[3 * q + 1], f[3 * q + 2], ux, xp);
-}
-
-// Collision when the free rates of orders 3..6 all equal 1: those moments
-// relax fully to equilibrium, so only the six second-order central moments of
-// the incoming populations are needed.  They follow from the raw second
-// moments P of f_hat:  dA_ab = P_ab - u_a j_b - u_b j_a + u_a u_b d rho
-// - delta_ab d rho / 3.  Post-collision deviations: order 0 d rho, order 1
-// rho g / 2 + u, order 2 (1 - s2) dA - s2 (T w), orders 3..6 -(T w).  The
-// inverse runs with every moment scaled by 1/2 per non-zero index (inv1h).
-template <class T>
-__device__ __forceinline__ void collide_rates_one(T (&f)[27], const T (&S0)[9], const T (&S1)[9],
-                                                  const T (&S2)[9], T drho, T jx, T jy, T jz,
-                                                  T ux, T uy, T uz, T hr, T om2, T s2,
-                                                  const T (&g)[3]) {
-    const T third = T(1) / T(3);
-    const T Pxx = ((S2[0] + S2[1]) + (S2[2] + S2[3])) + ((S2[4] + S2[5]) + (S2[6] + S2[7])) + S2[8];
-    const T Pxy = (S1[2] + S1[5] + S1[8]) - (S1[0] + S1[3] + S1[6]);
-    const T Pxz = (S1[6] + S1[7] + S1[8]) - (S1[0] + S1[1] + S1[2]);
-    const T Pyy = (S0[0] + S0[2]) + (S0[3] + S0[5]) + (S0[6] + S0[8]);
-    const T Pzz = (S0[0] + S0[1]) + (S0[2] + S0[6]) + (S0[7] + S0[8]);
-    const T Pyz = (S0[0] + S0[8]) - (S0[2] + S0[6]);
-    const T d3 = drho * third;
-    const T dxx = Pxx - T(2) * ux * jx + (ux * ux) * drho - d3;
-    const T dyy = Pyy - T(2) * uy * jy + (uy * uy) * drho - d3;
-    const T dzz = Pzz - T(2) * uz * jz + (uz * uz) * drho - d3;
-    const T dxy = Pxy - ux * jy - uy * jx + (ux * uy) * drho;
-    const T dxz = Pxz - ux * jz - uz * jx + (ux * uz) * drho;
-    const T dyz = Pyz - uy * jz - uz * jy + (uy * uz) * drho;
-
-    // half-scaled p: q = (1, -u/2, u^2/2)
-    const T qx[3] = {T(1), T(-0.5) * ux, T(0.5) * ux * ux};
-    const T qy[3] = {T(1), T(-0.5) * uy, T(0.5) * uy * uy};
-    const T qz[3] = {T(1), T(-0.5) * uz, T(0.5) * uz * uz};
-    const T hom2 = T(0.5) * om2, qom2 = T(0.25) * om2;
-    T m[27];
-    m[0] = drho;
-    m[1] = T(0.5) * (hr * g[0] + ux);
-    m[3] = T(0.5) * (hr * g[1] + uy);
-    m[9] = T(0.5) * (hr * g[2] + uz);
-    // order 2, scaled by 1/2 (one non-zero index) or 1/4 (two)
-    m[2] = hom2 * dxx - s2 * qx[2];
-    m[6] = hom2 * dyy - s2 * qy[2];
-    m[18] = hom2 * dzz - s2 * qz[2];
-    m[4] = qom2 * dxy - s2 * (qx[1] * qy[1]);
-    m[10] = qom2 * dxz - s2 * (qx[1] * qz[1]);
-    m[12] = qom2 * dyz - s2 * (qy[1] * qz[1]);
-    // orders 3..6 with 1 - s = 0: -(T w), scaled
-#pragma unroll
-    for (int mm = 0; mm < 27; ++mm) {
-        const int i = mm % 3, j = (mm / 3) % 3, k = mm / 9;
-        if (i + j + k >= 3) m[mm] = -(qx[i] * qy[j]) * qz[k];
-    }
-    const T uhz = T(0.5) * uz, u2z = T(2) * uz, u2pz = T(0.5) * (uz * uz + third);
-    const T uhy = T(0.5) * uy, u2y = T(2) * uy, u2py = T(0.5) * (uy * uy + third);
-    const T uhx = T(0.5) * ux, u2x = T(2) * ux, u2px = T(0.5) * (ux * ux + third);
-    // z pass; the lines (i, j) with i + j >= 3 hold -(T w) only and invert to
-    // -(q_i q_j) w1(cz)
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int i = q % 3, j = q / 3;
-        if (i + j >= 3) {
-            const T P = qx[i] * qy[j];
-            const T e = P * T(-1.0 / 6.0);
-            m[q] = e;
-            m[q + 9] = P * T(-2.0 / 3.0);
-            m[q + 18] = e;
-        } else {
-            inv1h(m[q], m[q + 9], m[q + 18], uhz, u2z, u2pz);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) inv1h(m[9 * k + i], m[9 * k + i + 3], m[9 * k + i + 6], uhy, u2y, u2py);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) inv1h(m[3 * q], m[3 * q + 1], m[3 * q + 2], uhx, u2x, u2px);
-#pragma unroll
-    for (int mm = 0; mm < 27; ++mm) f[mm] = m[mm];
-}
-
-// --- gather of the incoming populations -------------------------------------------
-struct __attribute__((aligned(8))) RowPair {
-    uint32_t w0;
-    int32_t p0;
-    uint32_t w1;
-    int32_t p1;
-};
-
-// Ordinary node: streaming and halfway bounce-back through the row table.
-// The nine row-table entries are loaded first and the population loads issued
-// after all of them (vector loads retire in order, so interleaving them would
-// serialize the rows).
-template <class S, bool PER, bool WALLS>
-__device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const StepArgs& a, int i,
-                                            uint32_t w, typename Traits<S>::T (&f)[27],
-                                            uint32_t& wallmask) {
-    constexpr uint32_t SZ = sizeof(S);
-    const uint32_t plane = (uint32_t)a.npad * SZ;
-    const uint32_t ib = (uint32_t)i * SZ;
-    const char* rt = (const char*)a.rowtab;
-    const int x = (int)(w & 1023u);
-    int y = 0, z = 0;
-    uint32_t e0 = 0;
-    if (!PER) {
-        e0 = (w >> 10) * (uint32_t)a.W + (uint32_t)(x >> 5);
-    } else {
-        y = (int)((w >> 10) & 1023u);
-        z = (int)((w >> 20) & 1023u);
-    }
-    const uint32_t sh = (uint32_t)x & 31u;
-    const uint32_t low = (uint32_t)((2ull << sh) - 1ull);
-    const int rowlen = a.ny + 2;
-    RowPair rp[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int ky = q % 3, kz = q / 3;
-        uint32_t e;
-        if (!PER) {
-            e = e0 - (uint32_t)(((ky - 1) + (kz - 1) * rowlen) * a.W);
-        } else {
-            int ys = y - (ky - 1), zs = z - (kz - 1);
-            if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
-            if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
-            e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
-        }
-        rp[q] = *(const RowPair*)(rt + e * 8u);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int ky = q % 3, kz = q / 3;
-        // bits of cells x - 1, x, x + 1 of this row
-        const uint32_t win = __builtin_amdgcn_alignbit(rp[q].w1, rp[q].w0, sh);
-        const int base = (q == 4) ? i : rp[q].p0 + (int)__popc(rp[q].w0 & low);
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int al = 9 * kz + 3 * ky + kx;
-            const int k = 2 - kx;              // bit of the source cell x - cx
-            if (al == 13) {
-                f[al] = ldp<S>(fin, 13u * plane + ib);
-                continue;
-            }
-            const bool fl = (win >> k) & 1u;
-            const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
-            const uint32_t off = fl ? (uint32_t)al * plane + (uint32_t)src * SZ
-                                    : (uint32_t)(26 - al) * plane + ib;
-            f[al] = ldp<S>(fin, off);
-            if (WALLS && !fl) wallmask |= 1u << al;
-        }
-    }
-}
-
-// Node with open-boundary or periodic-x links: explicit byte offsets, then the
-// open-boundary corrections with the additive terms prepared by the previous
-// step (or the initial state): inlet f_a = f*_abar + add, outlet
-// f_a = -f*_abar + add (evaluated in FP64, rounded once).
-template <class S, bool MON>
-__device__ __forceinline__ void gather_special(const char* __restrict__ fin, const StepArgs& a,
-                                               const SpecialNode* __restrict__ sp,
-                                               typename Traits<S>::T (&f)[27], double (&F)[3],
-                                               double& qin, double& qout) {
-    using T = typename Traits<S>::T;
-#pragma unroll
-    for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin, sp->off[al]);
-    const uint32_t wm = sp->wallmask, lm = sp->linkmask;
-    if (MON && wm) {
-#pragma unroll
-        for (int al = 0; al < 27; ++al) {
-            if ((wm >> al) & 1u) {
-                const double v = 2.0 * ((double)f[al] + wgt(al));
-                F[0] -= v * cxo(al);
-                F[1] -= v * cyo(al);
-                F[2] -= v * czo(al);
-            }
-        }
-    }
-    if (lm) {
-        int l = sp->link0;
-#pragma unroll
-        for (int al = 0; al < 27; ++al) {
-            if ((lm >> al) & 1u) {
-                const bool inlet = (a.link_meta[l] & 0xff) == LINK_INLET;
-                const double own = (double)f[al];
-                const T vt = (T)((inlet ? own : -own) + a.link_add[l]);
-                f[al] = vt;
-                if (MON) {
-                    const double q = (double)vt - own;
-                    if (inlet) qin += q;
-                    else qout += q;
-                }
-                ++l;
-            }
-        }
-    }
-}
-
-// Additive terms of a special node's open links for the step that streams the
-// populations of time t_next.  The inlet phase (cos, sin)(omega t_next) is read
-// from the device phase slots.
-__device__ __forceinline__ void update_links(const StepArgs& a, const SpecialNode* __restrict__ sp, double ux,
-                                          double uy, double uz, int64_t t_next) {
-    const int l0 = sp->link0, nl = __popc(sp->linkmask);
-    const double cw = a.trig[2 * (t_next & 1)], sw = a.trig[2 * (t_next & 1) + 1];
-    for (int l = l0; l < l0 + nl; ++l) {
-        const int meta = a.link_meta[l];
-        const int al = meta >> 8;
-        const double* cf = a.link_coef + LINK_COEFS * l;
-        double add;
-        if ((meta & 0xff) == LINK_INLET) {
-            const double U = cf[0] + cf[1] * cw - cf[2] * sw;
-            const double U2 = U * U;
-            add = U * (cf[3] + U2 * (cf[4] + U2 * cf[5]));
-        } else {
-            // f_eq_a + f_eq_abar = 2 rho_out (even part of prod_d (e_d + o_d)),
-            // e_d, o_d the even and odd parts of psi(c_d, u_d)
-            const int c[3] = {al % 3 - 1, (al / 3) % 3 - 1, al / 9 - 1};
-            const double u[3] = {ux, uy, uz};
-            double e[3], o[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double v = u[d];
-                e[d] = c[d] == 0 ? 2.0 / 3.0 - v * v : 0.5 * (1.0 / 3.0 + v * v);
-                o[d] = c[d] == 0 ? 0.0 : 0.5 * c[d] * v;
-            }
-            const double even = e[0] * e[1] * e[2] + e[0] * o[1] * o[2] + o[0] * e[1] * o[2] + o[0] * o[1] * e[2];
-            const double w = (c[0] == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (c[1] == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
-                             (c[2] == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
-            add = 2.0 * (a.rho_out * even - w);
-        }
-        a.link_add[l] = add;
-    }
-}
-
-// Advance the inlet phase: slot (t + 2) & 1 <- rotation of slot (t + 1) & 1 by
-// omega, renormalized to unit length.
-__device__ __forceinline__ void advance_phase(const StepArgs& a, int64_t t) {
-    const double* p = a.trig + 2 * ((t + 1) & 1);
-    const double c = p[0] * a.cos_w - p[1] * a.sin_w;
-    const double s = p[1] * a.cos_w + p[0] * a.sin_w;
-    const double r = 1.0 / sqrt(c * c + s * s);
-    double* q = a.trig + 2 * ((t + 2) & 1);
-    q[0] = c * r;
-    q[1] = s * r;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Fixed-order block reduction of 9 monitor values into out[0..8].
-__device__ __forceinline__ void block_monitor(double (&m)[9], double* __restrict__ out) {
-    __shared__ double red[BLOCK / 64][9];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = wave_sum(m[k]);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) red[wv][k] = m[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < 9) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < BLOCK / 64; ++q) s += red[q][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
-// Collision of the gathered populations (in place): moments, then one of the
-// two collision forms.  Returns the velocity and the conserved sums.
-template <class T, bool ONE>
-__device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T& uy, T& uz, T& drho,
-                                        T& jx, T& jy, T& jz) {
-    T S0[9], S1[9], S2[9];
-    line_sums(f, S0, S1, S2);
-    conserved(S0, S1, drho, jx, jy, jz);
-    T g[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) g[d] = (T)a.g[d];
-    const T rho = T(1) + drho;
-    const T inv = T(1) / rho;
-    const T hr = T(0.5) * rho;
-    ux = (jx + hr * g[0]) * inv;
-    uy = (jy + hr * g[1]) * inv;
-    uz = (jz + hr * g[2]) * inv;
-    if (ONE) {
-        collide_rates_one(f, S0, S1, S2, drho, jx, jy, jz, ux, uy, uz, hr, (T)(1.0 - a.s[0]), (T)a.s[0], g);
-    } else {
-        T om[5], sr[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            sr[k] = (T)a.s[k];
-            om[k] = (T)(1.0 - a.s[k]);
-        }
-        collide_general(f, drho, ux, uy, uz, hr, om, sr, g);
-    }
-}
-
-// --- the step kernel ----------------------------------------------------------------
+// One step over one domain.  XCD-aware order: hardware work-group b runs on
+// XCD (b % 8); each XCD gets a contiguous range of the node list, so
+// neighbouring rows share its L2.
 template <class S, bool MON, bool ONE, bool PER, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
-    using T = typename Traits<S>::T;
-    constexpr uint32_t SZ = sizeof(S);
-    // XCD-aware order: hardware work-group b runs on XCD (b % 8); give each XCD
-    // a contiguous range of the node list so neighbour rows share its L2.
     const int hb = blockIdx.x;
     const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
     if (lb >= a.nblocks) return;
-    const int i = lb * BLOCK + threadIdx.x;
-    const char* __restrict__ fin = (const char*)a.fin;
-    char* __restrict__ fout = (char*)a.fout;
-    double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < a.n) {
-        T f[27];
-        uint32_t wallmask = 0;
-        double F[3] = {0.0, 0.0, 0.0}, qin = 0.0, qout = 0.0;
-        const uint32_t w = a.node[i];
-        const SpecialNode* sp = nullptr;
-        if (!(w & SPECIAL_BIT)) {
-            gather_fast<S, PER, MON>(fin, a, i, w, f, wallmask);
-        } else {
-            sp = a.spec + (w & ~SPECIAL_BIT);
-            gather_special<S, MON>(fin, a, sp, f, F, qin, qout);
-        }
-        if (MON && wallmask) {
-            T fx = T(0), fy = T(0), fz = T(0);
-#pragma unroll
-            for (int al = 0; al < 27; ++al) {
-                if (al == 13) continue;
-                const T v = ((wallmask >> al) & 1u) ? f[al] + (T)wgt(al) : T(0);
-                if (cxo(al)) fx += cxo(al) > 0 ? v : -v;
-                if (cyo(al)) fy += cyo(al) > 0 ? v : -v;
-                if (czo(al)) fz += czo(al) > 0 ? v : -v;
-            }
-            F[0] -= 2.0 * (double)fx;
-            F[1] -= 2.0 * (double)fy;
-            F[2] -= 2.0 * (double)fz;
-        }
-        T ux, uy, uz, drho, jx, jy, jz;
-        collide<T, ONE>(f, a, ux, uy, uz, drho, jx, jy, jz);
-        if (MON) {
-            mon[0] = (double)drho;
-            mon[1] = (double)jx;
-            mon[2] = (double)jy;
-            mon[3] = (double)jz;
-            mon[4] = F[0];
-            mon[5] = F[1];
-            mon[6] = F[2];
-            mon[7] = qin;
-            mon[8] = qout;
-        }
-        const uint32_t plane = (uint32_t)a.npad * SZ;
-        const uint32_t ib = (uint32_t)i * SZ;
-#pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S, NT>(fout, (uint32_t)al * plane + ib, f[al]);
-        // after the stores, so the populations are no longer live
-        if (sp != nullptr && sp->linkmask != 0u)
-            update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);
-    }
-    if (lb == 0 && threadIdx.x == 0) {
-        const int64_t t = a.tcount[a.tin];
-        a.tcount[a.tin ^ 1] = t + 1;
-        advance_phase(a, t);
-    }
-    if (MON) block_monitor(mon, a.partials + (size_t)lb * MON_WORDS);
+    step_block<S, MON, ONE, PER, NT, BLOCK>(a, lb);
 }
 
 // Initial state: f(0) = f_eq(rho, u), then the first collision (written to

@@ -31,6 +31,8 @@ EXPORTED = [
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
     "lbm_average", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
     "lbm_inlet_profile", "lbm_destroy",
+    "lbm_batch_create", "lbm_batch_device_bytes", "lbm_batch_attach_device", "lbm_batch_config",
+    "lbm_batch_set_config", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_status", "lbm_batch_destroy",
 ]
 
 
@@ -80,6 +82,15 @@ def load():
         "lbm_set_state": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
         "lbm_inlet_profile": ([ctypes.c_double] * 7 + [ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "lbm_destroy": ([_P], None),
+        "lbm_batch_create": ([_P, ctypes.c_int, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "lbm_batch_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_batch_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
+        "lbm_batch_config": ([_P, _P], ctypes.c_int),
+        "lbm_batch_set_config": ([_P, _P], ctypes.c_int),
+        "lbm_batch_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "lbm_batch_step": ([_P, ctypes.c_int], ctypes.c_int),
+        "lbm_batch_status": ([_P], ctypes.c_int),
+        "lbm_batch_destroy": ([_P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -217,6 +228,54 @@ def lbm_destroy(dom) -> None:
         load().lbm_destroy(dom)
 
 
+def lbm_batch_create(doms, hip_stream: int):
+    arr = (_P * len(doms))(*[d.value if isinstance(d, _P) else d for d in doms])
+    out = _P()
+    _check(load().lbm_batch_create(arr, len(doms), _P(hip_stream), ctypes.byref(out)))
+    return out
+
+
+def lbm_batch_device_bytes(batch) -> int:
+    v = ctypes.c_size_t()
+    _check(load().lbm_batch_device_bytes(batch, ctypes.byref(v)))
+    return v.value
+
+
+def lbm_batch_attach_device(batch, dev_tensor) -> None:
+    _check(load().lbm_batch_attach_device(batch, _dptr(dev_tensor), dev_tensor.numel() * dev_tensor.element_size()))
+
+
+def lbm_batch_config(batch) -> list:
+    cfg = (ctypes.c_int * 5)()
+    _check(load().lbm_batch_config(batch, cfg))
+    return list(cfg)
+
+
+def lbm_batch_set_config(batch, cfg) -> None:
+    cfg = list(cfg) + [0] * (5 - len(cfg))
+    arr = (ctypes.c_int * 5)(*[int(v) for v in cfg])
+    _check(load().lbm_batch_set_config(batch, arr))
+
+
+def lbm_batch_autotune(batch, trial_steps: int, want_time: bool = False):
+    v = ctypes.c_double()
+    _check(load().lbm_batch_autotune(batch, int(trial_steps), ctypes.byref(v) if want_time else None))
+    return v.value if want_time else None
+
+
+def lbm_batch_step(batch, nsteps: int) -> None:
+    _check(load().lbm_batch_step(batch, int(nsteps)))
+
+
+def lbm_batch_status(batch) -> None:
+    _check(load().lbm_batch_status(batch))
+
+
+def lbm_batch_destroy(batch) -> None:
+    if batch:
+        load().lbm_batch_destroy(batch)
+
+
 # ---- convenience owner of a domain and its device memory ------------------------------
 
 class Domain:
@@ -314,6 +373,64 @@ class Domain:
         if self.handle:
             self.stream.synchronize()
             lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch of Domain objects plus the torch tensor holding the batch tables."""
+
+    def __init__(self, domains, stream=None):
+        import torch
+        self.torch = torch
+        self.domains = list(domains)
+        self.device = self.domains[0].device
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.handle = lbm_batch_create([d.handle for d in self.domains], self.stream.cuda_stream)
+        nbytes = lbm_batch_device_bytes(self.handle)
+        self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.mem.data_ptr()) % 256
+        self.mem.record_stream(self.stream)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        lbm_batch_attach_device(self.handle, self.mem[off: off + nbytes])
+
+    def _sync_in(self):
+        for d in self.domains:
+            self.stream.wait_stream(d.stream)
+
+    def _sync_out(self):
+        for d in self.domains:
+            d.stream.wait_stream(self.stream)
+
+    def autotune(self, trial_steps=32, want_time=False):
+        self._sync_in()
+        t = lbm_batch_autotune(self.handle, trial_steps, want_time)
+        self._sync_out()
+        return t
+
+    def step(self, n):
+        self._sync_in()
+        lbm_batch_step(self.handle, n)
+        self._sync_out()
+
+    def config(self):
+        return lbm_batch_config(self.handle)
+
+    def set_config(self, cfg):
+        lbm_batch_set_config(self.handle, cfg)
+
+    def status(self):
+        lbm_batch_status(self.handle)
+
+    def close(self):
+        if self.handle:
+            self.stream.synchronize()
+            lbm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
