@@ -92,6 +92,15 @@ def trilinear2(x):
     return out
 
 
+def bf16_round(x):
+    """Round to the nearest bfloat16 (ties to even) and return FP64: the value
+    is first rounded to FP32, then the low 16 bits of the FP32 pattern are
+    rounded away (finite inputs)."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def masked_mse(pred, target, mask):
     """Mean over masked voxels and the 3 components; returns (loss, dloss/dpred)."""
     m = mask.astype(np.float64)[..., None]
@@ -131,19 +140,29 @@ def init_params(seed=0):
     return p
 
 
-def forward(params, x):
-    """x: coarse input [d,h,w,4] = (u_c (3), mask_c) -> (fine velocity, cache)."""
-    cache = {}
+def _ident(a):
+    return a
+
+
+def forward(params, x, q=None):
+    """x: coarse input [d,h,w,4] = (u_c (3), mask_c) -> (fine velocity, cache).
+
+    q (optional) is a rounding applied where a reduced-precision implementation
+    stores values: the weights, the network input, every stored activation
+    (convolution outputs but the head's, the pooled tensor).  q = None is the
+    exact network."""
+    q = q or _ident
+    cache = {"q": q}
 
     def conv(name, inp, relu):
         w, b = params[name]
-        y = conv3d(inp, w, b)
-        out = np.maximum(y, 0.0) if relu else y
+        y = conv3d(inp, q(w), b)
+        out = q(np.maximum(y, 0.0)) if relu else y
         cache[name] = (inp, out)
         return out
 
-    e1 = conv("e1b", conv("e1a", x, True), True)
-    p = avgpool2(e1)
+    e1 = conv("e1b", conv("e1a", q(x), True), True)
+    p = q(avgpool2(e1))
     e2 = conv("e2c", conv("e2b", conv("e2a", p, True), True), True)
     u1 = conv("u1", upsample2(e2), True)
     cat = np.concatenate([e1, u1], axis=-1)
@@ -154,15 +173,19 @@ def forward(params, x):
 
 
 def backward(params, cache, dout):
-    """Parameter gradients {name: (dw, db)} for output gradient dout."""
+    """Parameter gradients {name: (dw, db)} for output gradient dout.  With the
+    rounding q of the forward pass, each layer's output gradient (after the
+    ReLU mask) is rounded before it meets the weights and the inputs; the bias
+    gradient sums the unrounded one."""
     grads = {}
+    q = cache["q"]
 
     def conv_b(name, dy, relu):
         inp, out = cache[name]
         if relu:
             dy = dy * (out > 0)
-        dx, dw, db = conv3d_backward(inp, params[name][0], dy)
-        grads[name] = (dw, db)
+        dx, dw, _ = conv3d_backward(inp, q(params[name][0]), q(dy))
+        grads[name] = (dw, dy.sum(axis=(0, 1, 2)))
         return dx
 
     d = conv_b("head", dout, False)

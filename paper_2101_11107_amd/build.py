@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_batch.hip", "lbm_api.cpp", "lbm_batch_api.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_batch.hip", "lbm_net.hip", "lbm_api.cpp", "lbm_batch_api.cpp", "lbm_net_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

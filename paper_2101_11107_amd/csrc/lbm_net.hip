@@ -1,0 +1,656 @@
+// HIP kernels of the learned coarse-to-fine velocity corrector (gfx950).
+//
+// Tensors are channels-last: element (sample s, voxel v, channel c) of a
+// tensor with row length ld sits at [(s * V + v) * ld + c], V = D * H * W and
+// v = (z * H + y) * W + x.  Convolutions are 3x3x3, stride 1, zero padded,
+// computed as implicit GEMMs on the matrix cores with
+// v_mfma_f32_16x16x16bf16_1k: BF16 operands, FP32 accumulation.  Lane l of a
+// wavefront holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16] and
+// D[4 (l / 16) + j][l % 16], j = 0..3.
+//
+// Forward:  Y[v][co] = b[co] + sum_{tap, ci} W[co][tap][ci] X[v + off(tap)][ci]
+//           (M = output channels, N = voxels, K = 27 * input channels ordered
+//           tap-major, so four consecutive K are four consecutive channels of
+//           one voxel: one 8-byte load per lane).
+// Gradient with respect to the input: the same kernel with the weights
+//           flipped in the taps and transposed in the channels.
+// Gradient with respect to the weights: M = output channels, N = (tap,
+//           input channel), K = voxels; per-chunk partial sums reduced in a
+//           fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_net_internal.h"
+
+namespace lbmnet_dev {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const __bf16 h = (__bf16)f;                // round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+constexpr int CONV_WAVES = 4;   // waves per work-group
+constexpr int CONV_VOX = 32;    // voxels per wave (two 16-voxel tiles in one row)
+
+// --- convolution forward (also used for the input gradient) --------------------
+template <int MT, bool F32OUT>
+__global__ __launch_bounds__(CONV_WAVES * 64) void k_conv_fwd(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int64_t V = (int64_t)a.d * a.h * a.w;
+    const int64_t total = (int64_t)a.n * V;
+    const int64_t vbase = ((int64_t)blockIdx.x * CONV_WAVES + wave) * CONV_VOX;
+    if (vbase >= total) return;
+    // each 16-voxel tile lies in one row (w is a multiple of 16): row coordinates are wave-uniform
+    int s[2], z[2], y[2], x[2];
+    bool valid[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t v0 = vbase + nt * 16;
+        valid[nt] = v0 < total;
+        const int64_t vv = valid[nt] ? v0 : 0;
+        s[nt] = (int)(vv / V);
+        const int64_t rr = vv - (int64_t)s[nt] * V;
+        z[nt] = (int)(rr / ((int64_t)a.h * a.w));
+        y[nt] = (int)((rr / a.w) % a.h);
+        x[nt] = (int)(rr % a.w) + r16;
+    }
+    v4f acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int K = 27 * a.cin;
+    for (int k0 = 0; k0 < a.kpad; k0 += 16) {
+        const int k = k0 + 4 * q;
+        const int tap = k / a.cin, ci = k - tap * a.cin;
+        const bool kin = k < K;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        v4s b[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int zz = z[nt] + dz, yy = y[nt] + dy, xx = x[nt] + dx;
+            const bool ok = kin && valid[nt] && zz >= 0 && zz < a.d && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w;
+            const int64_t vox = ((int64_t)s[nt] * V + ((int64_t)zz * a.h + yy) * a.w + xx);
+            b[nt] = ok ? *(const v4s*)(a.x + vox * a.ldx + a.cxo + ci) : v4s{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const v4s aw = *(const v4s*)(a.wt + (int64_t)(mt * 16 + r16) * a.kpad + k);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw, b[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        if (!valid[nt]) continue;
+        const int64_t vox = vbase + nt * 16 + r16;
+        if (vox >= total) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = mt * 16 + 4 * q + j;
+                if (co >= a.cout) continue;
+                float val = acc[mt][nt][j] + (a.bias ? a.bias[co] : 0.0f);
+                if (a.relu) val = val > 0.0f ? val : 0.0f;
+                const int64_t idx = vox * a.ldy + a.cyo + co;
+                if (F32OUT) ((float*)a.y)[idx] = val;
+                else ((uint16_t*)a.y)[idx] = f2bf(val);
+            }
+        }
+    }
+}
+
+// --- weight gradient ------------------------------------------------------------
+// Block: one chunk of voxels (blockIdx.x) and 16 N-tiles (blockIdx.y), 4 per wave.
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int64_t V = (int64_t)a.d * a.h * a.w;
+    const int64_t total = (int64_t)a.n * V;
+    const int N = 27 * a.cin;
+    const int ntile0 = blockIdx.y * 16 + wave * 4;
+    int tapn[4], cin_n[4];
+    bool nin[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int n = (ntile0 + t) * 16 + r16;
+        nin[t] = n < N;
+        tapn[t] = nin[t] ? n / a.cin : 0;
+        cin_n[t] = nin[t] ? n - tapn[t] * a.cin : 0;
+    }
+    v4f acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t c0 = (int64_t)blockIdx.x * a.chunk;
+    const int64_t c1 = c0 + a.chunk < total ? c0 + a.chunk : total;
+    for (int64_t k0 = c0; k0 < c1; k0 += 16) {
+        // 16 voxels in one row: wave-uniform row coordinates
+        const int s = (int)(k0 / V);
+        const int64_t rr = k0 - (int64_t)s * V;
+        const int z = (int)(rr / ((int64_t)a.h * a.w));
+        const int y = (int)((rr / a.w) % a.h);
+        const int x0 = (int)(rr % a.w) + 4 * q;
+        v4s am[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int co = mt * 16 + r16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                am[mt][j] = (co < a.cout) ? (short)a.dy[(k0 + 4 * q + j) * a.ldy + co] : (short)0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int tap = tapn[t];
+            const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int zz = z + dz, yy = y + dyy;
+            const bool rowok = nin[t] && zz >= 0 && zz < a.d && yy >= 0 && yy < a.h;
+            const int64_t rowbase = ((int64_t)s * V + ((int64_t)zz * a.h + yy) * a.w);
+            v4s bn;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xx = x0 + j + dx;
+                const bool ok = rowok && xx >= 0 && xx < a.w;
+                bn[j] = ok ? (short)a.x[(rowbase + xx) * a.ldx + a.cxo + cin_n[t]] : (short)0;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[mt], bn, acc[mt][t], 0, 0, 0);
+        }
+    }
+    float* part = a.part + (int64_t)blockIdx.x * a.mpad * a.npad;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int n = (ntile0 + t) * 16 + r16;
+            if (n >= a.npad) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) part[(mt * 16 + 4 * q + j) * a.npad + n] = acc[mt][t][j];
+        }
+}
+
+// dW[co][n] = sum over chunks (fixed order); only co < cout_param are written.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int mpad, int npad, int cout_param,
+                               int N, float* __restrict__ dw) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cout_param * N) return;
+    const int co = idx / N, n = idx - co * N;
+    float s = 0.0f;
+    for (int c = 0; c < nchunks; ++c) s += part[((int64_t)c * mpad + co) * npad + n];
+    dw[idx] = s;
+}
+
+// Bias gradient: per-chunk sums of dy over voxels, then a fixed-order reduce.
+__global__ void k_bias_partial(const float* __restrict__ g, int ld, int off, int cout, int64_t total, int64_t chunk,
+                               float* __restrict__ part) {
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
+    float s = 0.0f;
+    for (int64_t v = c0; v < c1; ++v) s += g[v * ld + off + co];
+    part[(int64_t)blockIdx.x * 64 + co] = s;
+}
+__global__ void k_bias_reduce(const float* __restrict__ part, int nchunks, int cout, float* __restrict__ db) {
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunks; ++c) s += part[c * 64 + co];
+    db[co] = s;
+}
+
+// Packed BF16 weights from FP32 masters w[co][tap][ci] (rows co >= cout_param zero):
+// forward wt[m][tap * cin + ci], input-gradient wd[ci][tap' * cout + co] = w[co][26 - tap'][ci].
+__global__ void k_prep_weights(const float* __restrict__ w, int cin, int cout_param, int cout, uint16_t* wt, int mpad,
+                               int kpad, uint16_t* wd, int mpad_d, int kpad_d) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < mpad * kpad) {
+        const int m = idx / kpad, k = idx - m * kpad;
+        float v = 0.0f;
+        if (m < cout_param && k < 27 * cin) v = w[(m * 27 + k / cin) * cin + k % cin];
+        wt[idx] = f2bf(v);
+    }
+    if (wd && idx < mpad_d * kpad_d) {
+        const int m = idx / kpad_d, k = idx - m * kpad_d;   // m = ci, k = tap' * cout + co
+        float v = 0.0f;
+        if (m < cin && k < 27 * cout) {
+            const int tp = k / cout, co = k - tp * cout;
+            if (co < cout_param) v = w[(co * 27 + (26 - tp)) * cin + m];
+        }
+        wd[idx] = f2bf(v);
+    }
+}
+
+// g (FP32, channels [off, off + c) of rows of length ld) times the ReLU mask of
+// act (BF16, same layout; null: no mask), written in place and as a packed
+// BF16 copy [v][c].
+__global__ void k_grad_relu_cast(float* __restrict__ g, int ldg, int offg, const uint16_t* __restrict__ act, int lda,
+                                 int offa, int c, int64_t total, uint16_t* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total * c) return;
+    const int64_t v = idx / c;
+    const int ch = (int)(idx - v * c);
+    float val = g[v * ldg + offg + ch];
+    if (act && !(bf2f(act[v * lda + offa + ch]) > 0.0f)) val = 0.0f;
+    g[v * ldg + offg + ch] = val;
+    out[v * c + ch] = f2bf(val);
+}
+
+__global__ void k_cast_input(const float* __restrict__ x, int64_t count, uint16_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = f2bf(x[i]);
+}
+
+// 2x2x2 average pooling of BF16 channels [off, off + c) (row ld) into packed [V/8][c].
+__global__ void k_avgpool_fwd(const uint16_t* __restrict__ x, int ld, int off, int c, int n, int d, int h, int w,
+                              uint16_t* __restrict__ y) {
+    const int d2 = d / 2, h2 = h / 2, w2 = w / 2;
+    const int64_t total = (int64_t)n * d2 * h2 * w2 * c;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t r = idx;
+    const int ch = (int)(r % c); r /= c;
+    const int X = (int)(r % w2); r /= w2;
+    const int Y = (int)(r % h2); r /= h2;
+    const int Z = (int)(r % d2);
+    const int s = (int)(r / d2);
+    float acc = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t v = (((int64_t)s * d + 2 * Z + (k >> 2)) * h + 2 * Y + ((k >> 1) & 1)) * w + 2 * X + (k & 1);
+        acc += bf2f(x[v * ld + off + ch]);
+    }
+    y[idx] = f2bf(acc * 0.125f);
+}
+
+// Adjoint of the pooling: g[child][off + ch] += gy[parent][ch] / 8 (FP32).
+__global__ void k_avgpool_bwd_add(const float* __restrict__ gy, int c, int n, int d, int h, int w, float* __restrict__ g,
+                                  int ld, int off) {
+    const int64_t total = (int64_t)n * d * h * w * c;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t r = idx;
+    const int ch = (int)(r % c); r /= c;
+    const int x = (int)(r % w); r /= w;
+    const int y = (int)(r % h); r /= h;
+    const int z = (int)(r % d);
+    const int s = (int)(r / d);
+    const int64_t p = (((int64_t)s * (d / 2) + z / 2) * (h / 2) + y / 2) * (w / 2) + x / 2;
+    const int64_t v = ((int64_t)s * d + z) * h * w + (int64_t)y * w + x;
+    g[v * ld + off + ch] += 0.125f * gy[p * c + ch];
+}
+
+// Nearest 2x upsampling of BF16 [V][c] (coarse dims d, h, w) into packed [8V][c].
+__global__ void k_upsample_fwd(const uint16_t* __restrict__ x, int c, int n, int d, int h, int w,
+                               uint16_t* __restrict__ y) {
+    const int D = 2 * d, H = 2 * h, W = 2 * w;
+    const int64_t total = (int64_t)n * D * H * W * c;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t r = idx;
+    const int ch = (int)(r % c); r /= c;
+    const int X = (int)(r % W); r /= W;
+    const int Y = (int)(r % H); r /= H;
+    const int Z = (int)(r % D);
+    const int s = (int)(r / D);
+    const int64_t p = (((int64_t)s * d + Z / 2) * h + Y / 2) * w + X / 2;
+    y[idx] = x[p * c + ch];
+}
+
+// Adjoint of the upsampling: g[parent][ch] = sum of the 8 children (FP32, packed).
+__global__ void k_upsample_bwd(const float* __restrict__ gy, int c, int n, int d, int h, int w, float* __restrict__ g) {
+    const int64_t total = (int64_t)n * d * h * w * c;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t r = idx;
+    const int ch = (int)(r % c); r /= c;
+    const int x = (int)(r % w); r /= w;
+    const int y = (int)(r % h); r /= h;
+    const int z = (int)(r % d);
+    const int s = (int)(r / d);
+    const int H = 2 * h, W = 2 * w;
+    float acc = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t v = (((int64_t)s * 2 * d + 2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+        acc += gy[v * c + ch];
+    }
+    g[idx] = acc;
+}
+
+// Fixed trilinear upsampling of channels 0..2 of the FP32 coarse input (row 4):
+// fine node 2i on coarse node i, odd nodes average their neighbours, the last
+// coarse node repeated.  Output FP32 [8V][ldo], ldo 3 or 4 (channel 3 zero).
+__global__ void k_trilinear(const float* __restrict__ x, int n, int d, int h, int w, float* __restrict__ y, int ldo) {
+    const int D = 2 * d, H = 2 * h, W = 2 * w;
+    const int64_t total = (int64_t)n * D * H * W;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t r = idx;
+    const int X = (int)(r % W); r /= W;
+    const int Y = (int)(r % H); r /= H;
+    const int Z = (int)(r % D);
+    const int s = (int)(r / D);
+    const int z0 = Z / 2, y0 = Y / 2, x0 = X / 2;
+    const int z1 = (Z & 1) ? (z0 + 1 < d ? z0 + 1 : d - 1) : z0;
+    const int y1 = (Y & 1) ? (y0 + 1 < h ? y0 + 1 : h - 1) : y0;
+    const int x1 = (X & 1) ? (x0 + 1 < w ? x0 + 1 : w - 1) : x0;
+    for (int c = 0; c < 3; ++c) {
+        auto at = [&](int zz, int yy, int xx) { return x[((((int64_t)s * d + zz) * h + yy) * w + xx) * 4 + c]; };
+        const float v = 0.125f * (at(z0, y0, x0) + at(z0, y0, x1) + at(z0, y1, x0) + at(z0, y1, x1) +
+                                  at(z1, y0, x0) + at(z1, y0, x1) + at(z1, y1, x0) + at(z1, y1, x1));
+        y[idx * ldo + c] = v;
+    }
+    if (ldo == 4) y[idx * 4 + 3] = 0.0f;
+}
+
+// out[v][c] = base[v][c] + r[v][c], c < 3 (rows: base and r 4, out 3).
+__global__ void k_add_residual(const float* __restrict__ base, const float* __restrict__ r, int64_t total,
+                               float* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total * 3) return;
+    const int64_t v = idx / 3;
+    const int c = (int)(idx - v * 3);
+    out[idx] = base[v * 4 + c] + r[v * 4 + c];
+}
+
+// Masked squared error: per-block partial sums of the mask count and of the
+// squared error (FP64), then the gradient dr = 2 (pred - target) mask / (3 count).
+__global__ void k_loss_partial(const float* __restrict__ base, const float* __restrict__ r,
+                               const float* __restrict__ target, const uint8_t* __restrict__ mask, int64_t total,
+                               double* __restrict__ part) {
+    __shared__ double s_cnt[256], s_err[256];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double cnt = 0.0, err = 0.0;
+    if (v < total && mask[v]) {
+        cnt = 1.0;
+        for (int c = 0; c < 3; ++c) {
+            const double d = (double)(base[v * 4 + c] + r[v * 4 + c]) - (double)target[v * 3 + c];
+            err += d * d;
+        }
+    }
+    s_cnt[threadIdx.x] = cnt;
+    s_err[threadIdx.x] = err;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + st];
+            s_err[threadIdx.x] += s_err[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s_cnt[0];
+        part[2 * blockIdx.x + 1] = s_err[0];
+    }
+}
+__global__ void k_loss_reduce(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double s_cnt[256], s_err[256];
+    double cnt = 0.0, err = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        cnt += part[2 * b];
+        err += part[2 * b + 1];
+    }
+    s_cnt[threadIdx.x] = cnt;
+    s_err[threadIdx.x] = err;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + st];
+            s_err[threadIdx.x] += s_err[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = s_cnt[0] * 3.0 > 1.0 ? s_cnt[0] * 3.0 : 1.0;
+        out[0] = s_err[0] / n;   // loss
+        out[1] = n;              // normalisation
+    }
+}
+__global__ void k_loss_grad(const float* __restrict__ base, const float* __restrict__ r,
+                            const float* __restrict__ target, const uint8_t* __restrict__ mask, int64_t total,
+                            const double* __restrict__ stats, float* __restrict__ dr) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total) return;
+    const float scale = (float)(2.0 / stats[1]);
+    for (int c = 0; c < 3; ++c) {
+        const float d = mask[v] ? (base[v * 4 + c] + r[v * 4 + c]) - target[v * 3 + c] : 0.0f;
+        dr[v * 4 + c] = scale * d;
+    }
+    dr[v * 4 + 3] = 0.0f;
+}
+
+// Adam (Kingma & Ba) on FP32 parameters: m, v moments, bias-corrected step.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t count, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Crops of a batch: coarse input (u, mask) and fine target (u, mask) around
+// per-sample coarse origins; zero outside the source fields.  The fine loss
+// mask excludes a margin next to the crop faces.
+__global__ void k_crop(const float* __restrict__ uc, const uint8_t* __restrict__ mc, int Dc, int Hc, int Wc,
+                       const float* __restrict__ uf, const uint8_t* __restrict__ mf, const int* __restrict__ origin,
+                       int n, int d, int h, int w, int margin, float* __restrict__ xin, float* __restrict__ tgt,
+                       uint8_t* __restrict__ tmask) {
+    const int64_t Vc = (int64_t)d * h * w, Vf = 8 * Vc;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n * Vc) {
+        const int s = (int)(idx / Vc);
+        int64_t r = idx - s * Vc;
+        const int x = (int)(r % w), y = (int)((r / w) % h), z = (int)(r / ((int64_t)w * h));
+        const int Z = origin[3 * s] + z, Y = origin[3 * s + 1] + y, X = origin[3 * s + 2] + x;
+        const bool in = Z >= 0 && Z < Dc && Y >= 0 && Y < Hc && X >= 0 && X < Wc;
+        const int64_t src = in ? ((int64_t)Z * Hc + Y) * Wc + X : 0;
+        for (int c = 0; c < 3; ++c) xin[idx * 4 + c] = in ? uc[src * 3 + c] : 0.0f;
+        xin[idx * 4 + 3] = in ? (float)mc[src] : 0.0f;
+    }
+    if (idx < n * Vf) {
+        const int s = (int)(idx / Vf);
+        int64_t r = idx - s * Vf;
+        const int W2 = 2 * w, H2 = 2 * h, D2 = 2 * d;
+        const int x = (int)(r % W2), y = (int)((r / W2) % H2), z = (int)(r / ((int64_t)W2 * H2));
+        const int Z = 2 * origin[3 * s] + z, Y = 2 * origin[3 * s + 1] + y, X = 2 * origin[3 * s + 2] + x;
+        const int Df = 2 * Dc, Hf = 2 * Hc, Wf = 2 * Wc;
+        const bool in = Z >= 0 && Z < Df && Y >= 0 && Y < Hf && X >= 0 && X < Wf;
+        const int64_t src = in ? ((int64_t)Z * Hf + Y) * Wf + X : 0;
+        for (int c = 0; c < 3; ++c) tgt[idx * 3 + c] = in ? uf[src * 3 + c] : 0.0f;
+        const bool inner = z >= margin && z < D2 - margin && y >= margin && y < H2 - margin && x >= margin &&
+                           x < W2 - margin;
+        tmask[idx] = (in && inner && mf[src]) ? 1 : 0;
+    }
+}
+
+// Scatter of scaled node values (component-major [3][count], FP64) at node
+// coordinates into a dense FP32 [D][H][W][3] field and a node mask.
+__global__ void k_scatter(const double* __restrict__ vals, const int32_t* __restrict__ xyz, int64_t count, int D,
+                          int H, int W, double scale, float* __restrict__ dense, uint8_t* __restrict__ mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    if (x < 0 || x >= W || y < 0 || y >= H || z < 0 || z >= D) return;
+    const int64_t v = ((int64_t)z * H + y) * W + x;
+    for (int c = 0; c < 3; ++c) dense[v * 3 + c] = (float)(scale * vals[c * count + i]);
+    mask[v] = 1;
+}
+
+// Gather of a dense FP32 [V][3] field at node coordinates into scaled [3][count] FP64.
+__global__ void k_gather(const float* __restrict__ dense, const int32_t* __restrict__ xyz, int64_t count, int D, int H,
+                         int W, double scale, double* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    const bool in = x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D;
+    const int64_t v = in ? ((int64_t)z * H + y) * W + x : 0;
+    for (int c = 0; c < 3; ++c) vals[c * count + i] = in ? scale * (double)dense[v * 3 + c] : 0.0;
+}
+
+__global__ void k_fill(uint32_t* p, int64_t nwords, uint32_t value) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = value;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t conv_forward(const ConvArgs& a, int mt, bool f32out, hipStream_t st) {
+    const int64_t total = (int64_t)a.n * a.d * a.h * a.w;
+    const unsigned grid = blocks_for(total, CONV_WAVES * CONV_VOX);
+    const dim3 block(CONV_WAVES * 64);
+    if (mt == 1 && f32out) hipLaunchKernelGGL((k_conv_fwd<1, true>), dim3(grid), block, 0, st, a);
+    else if (mt == 1) hipLaunchKernelGGL((k_conv_fwd<1, false>), dim3(grid), block, 0, st, a);
+    else if (mt == 2 && f32out) hipLaunchKernelGGL((k_conv_fwd<2, true>), dim3(grid), block, 0, st, a);
+    else if (mt == 2) hipLaunchKernelGGL((k_conv_fwd<2, false>), dim3(grid), block, 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st) {
+    const int ntiles = a.npad / 16;
+    const dim3 grid(nchunks, (ntiles + 15) / 16);
+    if (mt == 1) hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(256), 0, st, a);
+    else if (mt == 2) hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(256), 0, st, a);
+    else return hipErrorInvalidValue;
+    const int N = 27 * a.cin;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout_param * N, 256)), dim3(256), 0, st, a.part,
+                       nchunks, a.mpad, a.npad, cout_param, N, dw);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const float* g, int ld, int off, int cout, int64_t total, float* part, int nchunks, float* db,
+                     hipStream_t st) {
+    const int64_t chunk = (total + nchunks - 1) / nchunks;
+    hipLaunchKernelGGL(k_bias_partial, dim3(nchunks), dim3(64), 0, st, g, ld, off, cout, total, chunk, part);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, st, part, nchunks, cout, db);
+    return hipGetLastError();
+}
+
+hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint16_t* wt, int mpad, int kpad,
+                        uint16_t* wd, int mpad_d, int kpad_d, hipStream_t st) {
+    int64_t n = (int64_t)mpad * kpad;
+    if (wd && (int64_t)mpad_d * kpad_d > n) n = (int64_t)mpad_d * kpad_d;
+    hipLaunchKernelGGL(k_prep_weights, dim3(blocks_for(n, 256)), dim3(256), 0, st, w, cin, cout_param, cout, wt, mpad,
+                       kpad, wd, mpad_d, kpad_d);
+    return hipGetLastError();
+}
+
+hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
+                          uint16_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_relu_cast, dim3(blocks_for(total * c, 256)), dim3(256), 0, st, g, ldg, offg, act, lda,
+                       offa, c, total, out);
+    return hipGetLastError();
+}
+
+hipError_t cast_input(const float* x, int64_t count, uint16_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_input, dim3(blocks_for(count, 256)), dim3(256), 0, st, x, count, out);
+    return hipGetLastError();
+}
+
+hipError_t avgpool_fwd(const uint16_t* x, int ld, int off, int c, int n, int d, int h, int w, uint16_t* y,
+                       hipStream_t st) {
+    const int64_t total = (int64_t)n * (d / 2) * (h / 2) * (w / 2) * c;
+    hipLaunchKernelGGL(k_avgpool_fwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, x, ld, off, c, n, d, h, w, y);
+    return hipGetLastError();
+}
+
+hipError_t avgpool_bwd_add(const float* gy, int c, int n, int d, int h, int w, float* g, int ld, int off,
+                           hipStream_t st) {
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(k_avgpool_bwd_add, dim3(blocks_for(total, 256)), dim3(256), 0, st, gy, c, n, d, h, w, g, ld,
+                       off);
+    return hipGetLastError();
+}
+
+hipError_t upsample_fwd(const uint16_t* x, int c, int n, int d, int h, int w, uint16_t* y, hipStream_t st) {
+    const int64_t total = (int64_t)n * 8 * d * h * w * c;
+    hipLaunchKernelGGL(k_upsample_fwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, x, c, n, d, h, w, y);
+    return hipGetLastError();
+}
+
+hipError_t upsample_bwd(const float* gy, int c, int n, int d, int h, int w, float* g, hipStream_t st) {
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(k_upsample_bwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, gy, c, n, d, h, w, g);
+    return hipGetLastError();
+}
+
+hipError_t trilinear(const float* x, int n, int d, int h, int w, float* y, int ldo, hipStream_t st) {
+    const int64_t total = (int64_t)n * 8 * d * h * w;
+    hipLaunchKernelGGL(k_trilinear, dim3(blocks_for(total, 256)), dim3(256), 0, st, x, n, d, h, w, y, ldo);
+    return hipGetLastError();
+}
+
+hipError_t add_residual(const float* base, const float* r, int64_t total, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_residual, dim3(blocks_for(total * 3, 256)), dim3(256), 0, st, base, r, total, out);
+    return hipGetLastError();
+}
+
+hipError_t loss_and_grad(const float* base, const float* r, const float* target, const uint8_t* mask, int64_t total,
+                         double* part, double* stats, float* dr, hipStream_t st) {
+    const unsigned nb = blocks_for(total, 256);
+    hipLaunchKernelGGL(k_loss_partial, dim3(nb), dim3(256), 0, st, base, r, target, mask, total, part);
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, part, (int)nb, stats);
+    if (dr) hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, st, base, r, target, mask, total, stats, dr);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* w, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(count, 256)), dim3(256), 0, st, w, g, m, v, count, lr, b1, b2, eps, c1,
+                       c2);
+    return hipGetLastError();
+}
+
+hipError_t crop(const float* uc, const uint8_t* mc, int Dc, int Hc, int Wc, const float* uf, const uint8_t* mf,
+                const int* origin, int n, int d, int h, int w, int margin, float* xin, float* tgt, uint8_t* tmask,
+                hipStream_t st) {
+    const int64_t total = (int64_t)n * 8 * d * h * w;
+    hipLaunchKernelGGL(k_crop, dim3(blocks_for(total, 256)), dim3(256), 0, st, uc, mc, Dc, Hc, Wc, uf, mf, origin, n,
+                       d, h, w, margin, xin, tgt, tmask);
+    return hipGetLastError();
+}
+
+hipError_t scatter(const double* vals, const int32_t* xyz, int64_t count, int D, int H, int W, double scale,
+                   float* dense, uint8_t* mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(count, 256)), dim3(256), 0, st, vals, xyz, count, D, H, W, scale,
+                       dense, mask);
+    return hipGetLastError();
+}
+
+hipError_t gather(const float* dense, const int32_t* xyz, int64_t count, int D, int H, int W, double scale,
+                  double* vals, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(count, 256)), dim3(256), 0, st, dense, xyz, count, D, H, W, scale,
+                       vals);
+    return hipGetLastError();
+}
+
+hipError_t fill(void* p, size_t bytes, uint32_t value, hipStream_t st) {
+    const int64_t nw = (int64_t)(bytes / 4);
+    if (nw == 0) return hipSuccess;
+    unsigned blocks = blocks_for(nw, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, nw, value);
+    return hipGetLastError();
+}
+
+}  // namespace lbmnet_dev

@@ -33,6 +33,10 @@ EXPORTED = [
     "lbm_inlet_profile", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_device_bytes", "lbm_batch_attach_device", "lbm_batch_config",
     "lbm_batch_set_config", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_status", "lbm_batch_destroy",
+    "lbmnet_param_count", "lbmnet_layer_info", "lbmnet_create", "lbmnet_device_bytes", "lbmnet_attach_device",
+    "lbmnet_set_params", "lbmnet_get_params", "lbmnet_forward", "lbmnet_loss_grad", "lbmnet_adam_step",
+    "lbmnet_adam_count", "lbmnet_destroy", "lbmnet_conv3d_workspace", "lbmnet_conv3d", "lbmnet_scatter",
+    "lbmnet_gather", "lbmnet_crop", "lbmnet_trilinear",
 ]
 
 
@@ -91,6 +95,27 @@ def load():
         "lbm_batch_step": ([_P, ctypes.c_int], ctypes.c_int),
         "lbm_batch_status": ([_P], ctypes.c_int),
         "lbm_batch_destroy": ([_P], None),
+        "lbmnet_param_count": ([ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lbmnet_layer_info": ([ctypes.c_int, _P], ctypes.c_int),
+        "lbmnet_create": ([ctypes.c_int] * 5 + [_P, ctypes.POINTER(_P)], ctypes.c_int),
+        "lbmnet_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbmnet_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
+        "lbmnet_set_params": ([_P, _P], ctypes.c_int),
+        "lbmnet_get_params": ([_P, _P], ctypes.c_int),
+        "lbmnet_forward": ([_P, _P, _P], ctypes.c_int),
+        "lbmnet_loss_grad": ([_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+        "lbmnet_adam_step": ([_P] + [ctypes.c_float] * 4, ctypes.c_int),
+        "lbmnet_adam_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lbmnet_destroy": ([_P], ctypes.c_int),
+        "lbmnet_conv3d_workspace": ([ctypes.c_int] * 6 + [ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbmnet_conv3d": ([ctypes.c_int] * 7 + [_P] * 9 + [ctypes.c_size_t, _P], ctypes.c_int),
+        "lbmnet_scatter": ([_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                            _P, _P, _P], ctypes.c_int),
+        "lbmnet_gather": ([_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                           _P, _P], ctypes.c_int),
+        "lbmnet_crop": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P] + [ctypes.c_int] * 5
+                        + [_P, _P, _P, _P], ctypes.c_int),
+        "lbmnet_trilinear": ([_P] + [ctypes.c_int] * 4 + [_P, _P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

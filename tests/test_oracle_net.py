@@ -121,3 +121,36 @@ def test_parameter_count():
     p = o3.init_params(0)
     n = sum(w.size + b.size for w, b in p.values())
     assert 120_000 < n < 160_000
+
+
+def test_bf16_round_matches_torch_and_ties_to_even():
+    """The oracle's BF16 rounding agrees with torch's CPU conversion (round to
+    nearest, ties to even), including exact ties."""
+    import torch
+    rng = np.random.default_rng(20)
+    x = np.concatenate([rng.normal(size=2000), rng.normal(size=2000) * 1e-30, rng.normal(size=2000) * 1e30])
+    bits = rng.integers(0, 2 ** 31, 500, dtype=np.uint64)
+    ties = ((bits & 0x7F7F0000) | 0x8000).astype(np.uint32).view(np.float32).astype(np.float64)
+    x = np.concatenate([x, ties, -ties, [0.0, 1.0, -2.5]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(o3.bf16_round(x), ref)
+    # ties go to the even neighbour: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert o3.bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert o3.bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+
+
+def test_quantized_network_reduces_to_exact_with_identity():
+    """With q the identity the storage-rounded forward and backward are the
+    exact network; with BF16 rounding the output moves by about the BF16 step."""
+    params = o3.init_params(3)
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.normal(0, 0.3, (4, 4, 4, 3)), (rng.random((4, 4, 4, 1)) > 0.3)], axis=-1)
+    out, cache = o3.forward(params, x)
+    out_i, cache_i = o3.forward(params, x, q=lambda a: a)
+    assert np.array_equal(out, out_i)
+    g = o3.backward(params, cache, np.ones_like(out))
+    gi = o3.backward(params, cache_i, np.ones_like(out))
+    assert all(np.array_equal(g[k][0], gi[k][0]) and np.array_equal(g[k][1], gi[k][1]) for k in g)
+    out_q, _ = o3.forward(params, x, q=o3.bf16_round)
+    rel = np.linalg.norm(out_q - out) / np.linalg.norm(out)
+    assert 1e-5 < rel < 3e-2
