@@ -118,8 +118,8 @@ int lbmnet_destroy(lbmnet* net);
  * (FP32), dw = correlation of bf16(dz) with bf16(x), dx = the transposed
  * convolution of bf16(dz) with bf16(w); FP32 accumulation throughout.
  * x [n][d][h][w][cin], w [cout][27][cin], b [cout], dy and y [..][cout],
- * dx like x, dw like w, db like b: device FP32.  cin and cout multiples of 4
- * and at most 32, w a multiple of 16.  work: device scratch of
+ * dx like x, dw like w, db like b: device FP32.  cin a multiple of 4 and at
+ * most 32, cout one of 4, 8, 16, 32, w a multiple of 16.  work: device scratch of
  * lbmnet_conv3d_workspace bytes, 256-byte aligned.  Asynchronous. */
 int lbmnet_conv3d_workspace(int n, int d, int h, int w, int cin, int cout, size_t* bytes);
 int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const float* x, const float* wts,

@@ -102,14 +102,10 @@ class TrainResult:
     iters: int = 0
 
 
-def _crop_origin(rng, coarse_mask_np, crop):
-    zz, yy, xx = np.nonzero(coarse_mask_np)
-    k = int(rng.integers(0, zz.size))
-    shape = coarse_mask_np.shape
-    o = []
-    for c, s in zip((zz[k], yy[k], xx[k]), shape):
-        o.append(int(min(max(c - crop // 2, 0), max(s - crop, 0))))
-    return o
+def _crop_origin(rng, fluid_zyx, shape, crop):
+    """Origin (z, y, x) of a crop centred on a random fluid voxel, kept inside the grid."""
+    c = fluid_zyx[int(rng.integers(0, fluid_zyx.shape[0]))]
+    return [int(min(max(int(v) - crop // 2, 0), max(s - crop, 0))) for v, s in zip(c, shape)]
 
 
 def train(pairs: list, cfg: TrainConfig, params: np.ndarray | None = None, log=print) -> TrainResult:
@@ -124,14 +120,15 @@ def train(pairs: list, cfg: TrainConfig, params: np.ndarray | None = None, log=p
     tgt = torch.empty((cfg.batch, 2 * c, 2 * c, 2 * c, 3), dtype=torch.float32, device=dev)
     tmask = torch.empty((cfg.batch, 2 * c, 2 * c, 2 * c), dtype=torch.uint8, device=dev)
     origins = torch.empty((cfg.batch, 3), dtype=torch.int32, device=dev)
-    masks_np = [p.coarse.mask.cpu().numpy() for p in pairs]
+    fluid = [np.argwhere(p.coarse.mask.cpu().numpy()) for p in pairs]
+    shapes = [tuple(p.coarse.mask.shape) for p in pairs]
     res = TrainResult(params=None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = model.stream.cuda_stream
     for it in range(cfg.iters):
         picks = rng.integers(0, len(pairs), cfg.batch)
-        org = np.array([_crop_origin(rng, masks_np[k], c) for k in picks], np.int32)
+        org = np.array([_crop_origin(rng, fluid[k], shapes[k], c) for k in picks], np.int32)
         origins.copy_(torch.from_numpy(org))
         model._in()
         for s, k in enumerate(picks):
@@ -291,6 +288,9 @@ def run_protocol(train_seeds, test_seeds, cfg: TrainConfig, log=print) -> dict:
     thr = calibrate(ev_train)
     ev_test = [evaluate(tr.params, p, model) for p in pairs_test]
     model.close()
+    # run time of the fine run in the coarse run's storage type, for the speed comparison
+    from synth import aneurysm_case
+    fine_f32 = [period_average(aneurysm_case(2 * Dc, s), "f32").seconds for s in list(test_seeds)[:2]]
     fb = [falls_back(e, thr) for e in ev_test]
     # with a fallback the fine run is the answer: zero error against itself
     l2_eff = [0.0 if f else e.l2_net for e, f in zip(ev_test, fb)]
@@ -309,6 +309,10 @@ def run_protocol(train_seeds, test_seeds, cfg: TrainConfig, log=print) -> dict:
         "infer_seconds": float(np.mean([e.infer_seconds for e in ev_test])),
         "coarse_seconds": float(np.mean([e.coarse_seconds for e in ev_test])),
         "fine_seconds_f64": float(np.mean([e.fine_seconds for e in ev_test])),
+        "fine_seconds_f32": float(np.mean(fine_f32)),
+        "speedup_vs_fine_f32": float(np.mean(fine_f32) / (np.mean([e.coarse_seconds + e.infer_seconds
+                                                                  for e in ev_test]))),
+        "train_checks": [e.checks for e in ev_train], "test_checks": [e.checks for e in ev_test],
         "params": tr.params,
     }
 
@@ -319,10 +323,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train and score the coarse-to-fine corrector")
     ap.add_argument("--train", type=int, default=48, help="training seeds 0..train-1")
     ap.add_argument("--test", type=int, default=16, help="held-out seeds after the training seeds")
-    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--out", default=None, help="write the summary (JSON) and parameters (.npy) here")
     a = ap.parse_args(argv)
-    cfg = TrainConfig(iters=a.iters)
+    cfg = TrainConfig(iters=a.iters, log_every=max(1, a.iters // 10))
     res = run_protocol(range(a.train), range(a.train, a.train + a.test), cfg,
                        log=lambda m: print(m, flush=True))
     params = res.pop("params")

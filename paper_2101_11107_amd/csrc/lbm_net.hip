@@ -183,34 +183,46 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
         }
 }
 
-// dW[co][n] = sum over chunks (fixed order); only co < cout_param are written.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int mpad, int npad, int cout_param,
-                               int N, float* __restrict__ dw) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cout_param * N) return;
-    const int co = idx / N, n = idx - co * N;
-    float s = 0.0f;
-    for (int c = 0; c < nchunks; ++c) s += part[((int64_t)c * mpad + co) * npad + n];
-    dw[idx] = s;
+// dW[co][n] = sum over chunks, only co < cout_param written.  A work-group
+// covers 32 outputs; each of its 8 thread groups sums every 8th chunk in
+// ascending order, then the 8 group sums are added in order (deterministic).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int mpad, int npad,
+                                                      int cout_param, int N, float* __restrict__ dw) {
+    __shared__ float s[8][32];
+    const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + lane;
+    const int E = cout_param * N;
+    float acc = 0.0f;
+    if (e < E) {
+        const int co = e / N, n = e - co * N;
+        const float* p = part + (int64_t)co * npad + n;
+        const int64_t stride = (int64_t)mpad * npad;
+        for (int c = grp; c < nchunks; c += 8) acc += p[c * stride];
+    }
+    s[grp][lane] = acc;
+    __syncthreads();
+    if (grp == 0 && e < E) {
+        float t = s[0][lane];
+        for (int k = 1; k < 8; ++k) t += s[k][lane];
+        dw[e] = t;
+    }
 }
 
-// Bias gradient: per-chunk sums of dy over voxels, then a fixed-order reduce.
-__global__ void k_bias_partial(const float* __restrict__ g, int ld, int off, int cout, int64_t total, int64_t chunk,
-                               float* __restrict__ part) {
-    const int co = threadIdx.x;
-    if (co >= cout) return;
-    const int64_t c0 = (int64_t)blockIdx.x * chunk;
-    const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
-    float s = 0.0f;
-    for (int64_t v = c0; v < c1; ++v) s += g[v * ld + off + co];
-    part[(int64_t)blockIdx.x * 64 + co] = s;
-}
-__global__ void k_bias_reduce(const float* __restrict__ part, int nchunks, int cout, float* __restrict__ db) {
-    const int co = threadIdx.x;
-    if (co >= cout) return;
-    float s = 0.0f;
-    for (int c = 0; c < nchunks; ++c) s += part[c * 64 + co];
-    db[co] = s;
+// Bias gradient from the per-work-group channel sums of k_grad_relu_cast: one
+// work-group per channel, fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ part, int nparts,
+                                                     float* __restrict__ db) {
+    __shared__ float s[256];
+    const int co = blockIdx.x;
+    float acc = 0.0f;
+    for (int b = threadIdx.x; b < nparts; b += 256) acc += part[b * 64 + co];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = s[0];
 }
 
 // Packed BF16 weights from FP32 masters w[co][tap][ci] (rows co >= cout_param zero):
@@ -237,17 +249,34 @@ __global__ void k_prep_weights(const float* __restrict__ w, int cin, int cout_pa
 
 // g (FP32, channels [off, off + c) of rows of length ld) times the ReLU mask of
 // act (BF16, same layout; null: no mask), written in place and as a packed
-// BF16 copy [v][c].
-__global__ void k_grad_relu_cast(float* __restrict__ g, int ldg, int offg, const uint16_t* __restrict__ act, int lda,
-                                 int offa, int c, int64_t total, uint16_t* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total * c) return;
-    const int64_t v = idx / c;
-    const int ch = (int)(idx - v * c);
-    float val = g[v * ldg + offg + ch];
-    if (act && !(bf2f(act[v * lda + offa + ch]) > 0.0f)) val = 0.0f;
-    g[v * ldg + offg + ch] = val;
-    out[v * c + ch] = f2bf(val);
+// BF16 copy [v][c]; per work-group channel sums of the masked FP32 values go to
+// part[block][0..c) for the bias gradient.  c divides 256 and `per` (elements
+// per work-group) is a multiple of 256, so a thread always sees one channel.
+__global__ __launch_bounds__(256) void k_grad_relu_cast(float* __restrict__ g, int ldg, int offg,
+                                                        const uint16_t* __restrict__ act, int lda, int offa, int c,
+                                                        int64_t total, int64_t per, uint16_t* __restrict__ out,
+                                                        float* __restrict__ part) {
+    __shared__ float s[256];
+    const int64_t E = total * c;
+    const int64_t e0 = (int64_t)blockIdx.x * per;
+    const int64_t e1 = e0 + per < E ? e0 + per : E;
+    float acc = 0.0f;
+    for (int64_t idx = e0 + threadIdx.x; idx < e1; idx += 256) {
+        const int64_t v = idx / c;
+        const int ch = (int)(idx - v * c);
+        float val = g[v * ldg + offg + ch];
+        if (act && !(bf2f(act[v * lda + offa + ch]) > 0.0f)) val = 0.0f;
+        g[v * ldg + offg + ch] = val;
+        out[idx] = f2bf(val);
+        acc += val;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st >= c; st >>= 1) {   // partners differ by a multiple of c: same channel
+        if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < c) part[(int64_t)blockIdx.x * 64 + threadIdx.x] = s[threadIdx.x];
 }
 
 __global__ void k_cast_input(const float* __restrict__ x, int64_t count, uint16_t* __restrict__ out) {
@@ -293,21 +322,23 @@ __global__ void k_avgpool_bwd_add(const float* __restrict__ gy, int c, int n, in
     g[v * ld + off + ch] += 0.125f * gy[p * c + ch];
 }
 
-// Nearest 2x upsampling of BF16 [V][c] (coarse dims d, h, w) into packed [8V][c].
+// Nearest 2x upsampling of BF16 [V][c] (coarse dims d, h, w) into packed
+// [8V][c]; c a multiple of 8, copied in 16-byte pieces.
 __global__ void k_upsample_fwd(const uint16_t* __restrict__ x, int c, int n, int d, int h, int w,
                                uint16_t* __restrict__ y) {
     const int D = 2 * d, H = 2 * h, W = 2 * w;
-    const int64_t total = (int64_t)n * D * H * W * c;
+    const int c8 = c / 8;
+    const int64_t total = (int64_t)n * D * H * W * c8;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     int64_t r = idx;
-    const int ch = (int)(r % c); r /= c;
+    const int part = (int)(r % c8); r /= c8;
     const int X = (int)(r % W); r /= W;
     const int Y = (int)(r % H); r /= H;
     const int Z = (int)(r % D);
     const int s = (int)(r / D);
     const int64_t p = (((int64_t)s * d + Z / 2) * h + Y / 2) * w + X / 2;
-    y[idx] = x[p * c + ch];
+    ((uint4*)y)[idx] = ((const uint4*)x)[p * c8 + part];
 }
 
 // Adjoint of the upsampling: g[parent][ch] = sum of the 8 children (FP32, packed).
@@ -533,16 +564,8 @@ hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, f
     else if (mt == 2) hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(256), 0, st, a);
     else return hipErrorInvalidValue;
     const int N = 27 * a.cin;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout_param * N, 256)), dim3(256), 0, st, a.part,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout_param * N, 32)), dim3(256), 0, st, a.part,
                        nchunks, a.mpad, a.npad, cout_param, N, dw);
-    return hipGetLastError();
-}
-
-hipError_t bias_grad(const float* g, int ld, int off, int cout, int64_t total, float* part, int nchunks, float* db,
-                     hipStream_t st) {
-    const int64_t chunk = (total + nchunks - 1) / nchunks;
-    hipLaunchKernelGGL(k_bias_partial, dim3(nchunks), dim3(64), 0, st, g, ld, off, cout, total, chunk, part);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, st, part, nchunks, cout, db);
     return hipGetLastError();
 }
 
@@ -556,9 +579,18 @@ hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint1
 }
 
 hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_relu_cast, dim3(blocks_for(total * c, 256)), dim3(256), 0, st, g, ldg, offg, act, lda,
-                       offa, c, total, out);
+                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st) {
+    if (c <= 0 || 256 % c != 0 || cout_param > c) return hipErrorInvalidValue;
+    const int64_t E = total * c;
+    int64_t nb = (E + 4095) / 4096;
+    if (nb > BIAS_PARTS) nb = BIAS_PARTS;
+    if (nb < 1) nb = 1;
+    const int64_t per = ((E + nb - 1) / nb + 255) / 256 * 256;
+    nb = (E + per - 1) / per;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_grad_relu_cast, dim3((unsigned)nb), dim3(256), 0, st, g, ldg, offg, act, lda, offa, c, total,
+                       per, out, part);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(cout_param), dim3(256), 0, st, part, (int)nb, db);
     return hipGetLastError();
 }
 
@@ -583,7 +615,8 @@ hipError_t avgpool_bwd_add(const float* gy, int c, int n, int d, int h, int w, f
 }
 
 hipError_t upsample_fwd(const uint16_t* x, int c, int n, int d, int h, int w, uint16_t* y, hipStream_t st) {
-    const int64_t total = (int64_t)n * 8 * d * h * w * c;
+    if (c % 8 != 0) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)n * 8 * d * h * w * (c / 8);
     hipLaunchKernelGGL(k_upsample_fwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, x, c, n, d, h, w, y);
     return hipGetLastError();
 }

@@ -70,10 +70,6 @@ int64_t wgrad_chunk(int64_t total) {
     c = (c + 15) / 16 * 16;
     return c < 256 ? 256 : c;
 }
-int bias_chunks(int64_t total) {
-    int64_t c = (total + 255) / 256;
-    return (int)(c > 1024 ? 1024 : (c < 1 ? 1 : c));
-}
 
 // Sizes of one layer-level grid.
 struct Level {
@@ -163,7 +159,6 @@ void plan(lbmnet* net) {
         net->o_gh16 = take(F * Vh * 16);
         net->o_gpkh = take(B * Vh * 32);
         size_t wpart = 0;
-        int64_t maxvox = 0;
         for (int i = 0; i < LBMNET_LAYERS; ++i) {
             const LayerGeom& g = net->lg[i];
             const int64_t tot = net->lev[LAYERS[i].level].vox();
@@ -171,10 +166,9 @@ void plan(lbmnet* net) {
             const int64_t nchunks = (tot + chunk - 1) / chunk;
             const size_t s = F * nchunks * g.mpad * g.npad;
             if (s > wpart) wpart = s;
-            if (tot > maxvox) maxvox = tot;
         }
         net->o_wpart = take(wpart);
-        net->o_bpart = take(F * 64 * (size_t)bias_chunks(maxvox));
+        net->o_bpart = take(F * 64 * (size_t)nd::BIAS_PARTS);
         net->o_lpart = take(sizeof(double) * 2 * (size_t)((Vf + 255) / 256));
         net->o_stats = take(sizeof(double) * 2);
     }
@@ -213,10 +207,10 @@ hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, cons
     const LayerGeom& G = net->lg[li];
     const Level& L = net->lev[LAYERS[li].level];
     const int64_t tot = L.vox();
-    hipError_t e = nd::grad_relu_cast(g, ldg, offg, LAYERS[li].relu ? act : nullptr, lda, offa, G.cout, tot, packed,
-                                      net->stream);
-    if (e != hipSuccess) return e;
     float* grad = net->at<float>(net->o_grad);
+    hipError_t e = nd::grad_relu_cast(g, ldg, offg, LAYERS[li].relu ? act : nullptr, lda, offa, G.cout, tot, packed,
+                                      net->at<float>(net->o_bpart), G.cout_param, grad + G.off_b, net->stream);
+    if (e != hipSuccess) return e;
     // weight gradient
     nd::WgradArgs w;
     w.dy = packed;
@@ -233,9 +227,6 @@ hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, cons
     w.chunk = wgrad_chunk(tot);
     const int nchunks = (int)((tot + w.chunk - 1) / w.chunk);
     e = nd::conv_wgrad(w, G.mt, nchunks, G.cout_param, grad + G.off_w, net->stream);
-    if (e != hipSuccess) return e;
-    e = nd::bias_grad(g, ldg, offg, G.cout_param, tot, net->at<float>(net->o_bpart), bias_chunks(tot),
-                      grad + G.off_b, net->stream);
     if (e != hipSuccess) return e;
     if (!dx) return hipSuccess;
     // input gradient: the forward kernel with the flipped, transposed weights
@@ -524,7 +515,7 @@ struct ConvWork {
 };
 bool conv_sizes_ok(int n, int d, int h, int w, int cin, int cout) {
     return n >= 1 && d >= 1 && h >= 1 && w >= 16 && w % 16 == 0 && cin >= 4 && cin <= 32 && cin % 4 == 0 &&
-           cout >= 4 && cout <= 32 && cout % 4 == 0 && (int64_t)n * d * h * w * 32 < ((int64_t)1 << 31);
+           (cout == 4 || cout == 8 || cout == 16 || cout == 32) && (int64_t)n * d * h * w * 32 < ((int64_t)1 << 31);
 }
 ConvWork conv_work(int n, int d, int h, int w, int cin, int cout) {
     const int64_t V = (int64_t)n * d * h * w;
@@ -545,7 +536,7 @@ ConvWork conv_work(int n, int d, int h, int w, int cin, int cout) {
     c.g = take(4 * V * cout);
     c.gb = take(2 * V * cout);
     c.wpart = take(4 * (size_t)nchunks * mpad * ceil16(27 * cin));
-    c.bpart = take(4 * 64 * (size_t)bias_chunks(V));
+    c.bpart = take(4 * 64 * (size_t)nd::BIAS_PARTS);
     c.total = off;
     return c;
 }
@@ -594,7 +585,9 @@ int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const
     a.y = yb;
     HIP_TRY(nd::conv_forward(a, mt, false, st), "lbmnet_conv3d forward (BF16 copy)");
     HIP_TRY(hipMemcpyAsync(g, dy, sizeof(float) * V * cout, hipMemcpyDeviceToDevice, st), "lbmnet_conv3d copy");
-    HIP_TRY(nd::grad_relu_cast(g, cout, 0, relu ? yb : nullptr, cout, 0, cout, V, gb, st), "lbmnet_conv3d mask");
+    HIP_TRY(nd::grad_relu_cast(g, cout, 0, relu ? yb : nullptr, cout, 0, cout, V, gb, (float*)(base + cw.bpart), cout,
+                               db, st),
+            "lbmnet_conv3d mask and bias gradient");
     nd::WgradArgs wa;
     wa.dy = gb;
     wa.x = xb;
@@ -605,8 +598,6 @@ int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const
     wa.chunk = wgrad_chunk(V);
     const int nchunks = (int)((V + wa.chunk - 1) / wa.chunk);
     HIP_TRY(nd::conv_wgrad(wa, mt, nchunks, cout, dw, st), "lbmnet_conv3d weight gradient");
-    HIP_TRY(nd::bias_grad(g, cout, 0, cout, V, (float*)(base + cw.bpart), bias_chunks(V), db, st),
-            "lbmnet_conv3d bias gradient");
     nd::ConvArgs t;
     t.x = gb;
     t.wt = wd;

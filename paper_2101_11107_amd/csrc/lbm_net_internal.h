@@ -8,6 +8,8 @@
 
 namespace lbmnet_dev {
 
+constexpr int BIAS_PARTS = 1024;   // work-groups of the bias-gradient sums
+
 // 3x3x3 convolution as an implicit GEMM.  x: BF16 channels [cxo, cxo + cin)
 // of rows of length ldx; wt: BF16 [mpad][kpad], K = 27 cin tap-major (zero
 // padded); y: rows of length ldy, channels [cyo, cyo + cout), FP32 or BF16.
@@ -37,12 +39,12 @@ struct WgradArgs {
 
 hipError_t conv_forward(const ConvArgs& a, int mt, bool f32out, hipStream_t st);
 hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st);
-hipError_t bias_grad(const float* g, int ld, int off, int cout, int64_t total, float* part, int nchunks, float* db,
-                     hipStream_t st);
 hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint16_t* wt, int mpad, int kpad,
                         uint16_t* wd, int mpad_d, int kpad_d, hipStream_t st);
+// Masked gradient (in place), its packed BF16 copy and the bias gradient db
+// (channels < cout_param).  part: FP32 scratch of BIAS_PARTS * 64 values.
 hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, hipStream_t st);
+                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st);
 hipError_t cast_input(const float* x, int64_t count, uint16_t* out, hipStream_t st);
 hipError_t avgpool_fwd(const uint16_t* x, int ld, int off, int c, int n, int d, int h, int w, uint16_t* y,
                        hipStream_t st);
