@@ -10,7 +10,9 @@ Prints one JSON line: fluid-node MLUPS, the roofline of the step kernel
 (algorithmic bytes 54 populations x storage bytes per node update), the FP64
 CPU oracle timed on a bounded sample on the host cores, and (``also``) the
 other storage forms and the 512^3 geometry with their velocity error against
-the FP64 run of the same geometry.
+the FP64 run of the same geometry, the batch of 48 uneven geometries, and the
+learned coarse-to-fine corrector (a reduced training protocol) with its
+velocity error against the FP64 fine run beside the trilinear upsampling.
 """
 
 import argparse
@@ -31,7 +33,7 @@ STEP_KERNEL = "k_step"
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_internal.h"):
+    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
         with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -132,6 +134,30 @@ def batch_bench(torch, lbm, steps, storage="f16s"):
             "roofline_frac": roofline(total, ms, storage, None)["frac"]}
 
 
+def corrector_bench():
+    """Reduced protocol of the learned corrector: 12 training geometries, 1500
+    Adam steps, 3 held-out geometries scored against their FP64 fine runs."""
+    import numpy as np
+    from paper_2101_11107_amd import corrector as C
+    from synth import aneurysm_case
+    train = [C.make_pair(s) for s in range(12)]
+    test = [C.make_pair(s) for s in (48, 49, 50)]
+    tr = C.train(train, C.TrainConfig(iters=1500, log_every=1500), log=None)
+    ev = [C.evaluate(tr.params, p) for p in test]
+    fine_f32 = C.period_average(aneurysm_case(256, 48), "f32").seconds
+    return {"workload": "corrector_aneurysm128_to_256", "train_geometries": 12, "held_out_geometries": 3,
+            "adam_steps": tr.iters, "train_seconds": round(tr.seconds, 2),
+            "ms_per_train_step": round(1e3 * tr.seconds / tr.iters, 2),
+            "u_rel_l2_net_vs_f64_fine": round(float(np.mean([e.l2_net for e in ev])), 5),
+            "u_rel_l2_trilinear_vs_f64_fine": round(float(np.mean([e.l2_tri for e in ev])), 5),
+            "similarity_index_net": round(float(np.mean([e.si_net for e in ev])), 5),
+            "similarity_index_trilinear": round(float(np.mean([e.si_tri for e in ev])), 5),
+            "coarse_run_s": round(float(np.mean([e.coarse_seconds for e in ev])), 4),
+            "inference_s": round(float(np.mean([e.infer_seconds for e in ev])), 4),
+            "fine_run_f32_s": round(fine_f32, 4),
+            "fine_run_f64_s": round(float(np.mean([e.fine_seconds for e in ev])), 4)}
+
+
 def roofline(n, ms_per_step, storage, traffic):
     alg = 54 * POP_BYTES[storage] * n                 # algorithmic bytes per launch
     achieved = alg / (ms_per_step * 1e-3) / 1e9
@@ -174,6 +200,7 @@ def main():
                     help="geometry of the timed run (profiling runs use the 512^3 one)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other storage forms and sizes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector protocol")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
@@ -241,13 +268,23 @@ def main():
                          "u_rel_l2_vs_f64": rel_l2(r["u"], ref["u"]),
                          "mass_drift_vs_f64": abs(r["monitors"][0] - ref["monitors"][0]) / ref["monitors"][0]})
         big = synth.aneurysm_case(512, seed=0)
-        for st in ("f32", "f16s", "bf16s", "f64"):
-            r = run_form(torch, lbm, big, st, 100, steps_x)
+        ref_big = None
+        for st in ("f64", "f32", "f16s", "bf16s"):
+            r = run_form(torch, lbm, big, st, 100, steps_x, want_u=True)
             rf = roofline(r["n"], r["ms_per_step"], st, read_traffic(st, "aneurysm512"))
-            also.append({"workload": "aneurysm512", "storage": st, "fluid_nodes": r["n"],
-                         "mlups": round(r["mlups"], 1), "achieved_GBs": rf["achieved"],
-                         "roofline_frac": rf["frac"], "traffic": rf["traffic"], "steps": steps_x})
+            row = {"workload": "aneurysm512", "storage": st, "fluid_nodes": r["n"],
+                   "mlups": round(r["mlups"], 1), "achieved_GBs": rf["achieved"],
+                   "roofline_frac": rf["frac"], "traffic": rf["traffic"], "steps": 100 + steps_x}
+            if ref_big is None:
+                ref_big = r
+            else:
+                row["u_rel_l2_vs_f64"] = rel_l2(r["u"], ref_big["u"])
+                row["mass_drift_vs_f64"] = abs(r["monitors"][0] - ref_big["monitors"][0]) / ref_big["monitors"][0]
+            also.append(row)
+        del ref_big
         also.append(batch_bench(torch, lbm, 480))
+        if not args.no_corrector:
+            also.append(corrector_bench())
         line["also"] = also
 
     if not args.no_cpu_baseline:
