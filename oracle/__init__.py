@@ -14,4 +14,9 @@ Two independent tiers, both written from the paper's equations:
 * ``o2`` (plain C + OpenMP, ``o2_fast.c``) -- the fast tier used at full
   sizes: factored per-axis transforms, same push streaming.  Checked against
   ``o1_dense`` by brute force on tiny random inputs.
+* ``o3_net`` (numpy) -- the learned corrector's network in FP64: 3x3x3
+  convolution and its gradients, pooling, upsampling, the trilinear base, the
+  masked loss, Adam, and the whole U-net forward and backward (with an
+  optional rounding hook at the points where a reduced-precision
+  implementation stores values).
 """

@@ -65,3 +65,25 @@ def test_network_argument_checks():
             nn.lbmnet_conv3d_workspace(*bad)
         assert e.value.code == lbm.LBM_EINVAL
     assert nn.lbmnet_conv3d_workspace(1, 2, 2, 16, 4, 4) > 0
+
+
+def test_library_womersley_profile_matches_closed_form():
+    """The library's host-side Womersley profile (its own complex J0 series)
+    against the closed form evaluated with scipy's Bessel function (the
+    oracle's definition), across radii, phases and Womersley numbers 1-8."""
+    import math
+    import numpy as np
+    from oracle import o1_dense as o1
+    from paper_2101_11107_amd import lbm
+    R = 12.0
+    for alpha in (1.0, 3.0, 8.0):
+        omega = 2 * math.pi / 4000.0
+        nu = omega * R * R / alpha ** 2
+        G0 = 4 * nu * 0.0329 / (R * R)
+        for t in (0.0, 517.0, 1999.0, 3333.0):
+            rs = np.array([0.0, 1.5, 6.0, 11.0, 11.99, 12.0, 13.0])
+            ref = o1.womersley_speed(rs, t, R, nu, G0, G0, omega)
+            got = np.array([lbm.lbm_inlet_profile(r, t, R, nu, G0, G0, omega) for r in rs])
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)) + 1e-18, (alpha, t)
+    # omega = 0: steady Poiseuille
+    assert abs(lbm.lbm_inlet_profile(3.0, 0.0, R, 0.02, 1e-6, 0.0, 0.0) - 1e-6 * (R * R - 9.0) / 0.08) < 1e-15
