@@ -60,14 +60,19 @@ template <> struct Traits<__bf16> {
 };
 
 // Load / store of one population at a byte offset from a uniform base.
+// Population and table pointers reach the step as kernel arguments or, for
+// batched stepping, from an argument table in memory; the explicit global
+// address space keeps the accesses global (not generic flat) in both cases.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+
 template <class S>
-__device__ __forceinline__ typename Traits<S>::T ldp(const char* __restrict__ base, uint32_t off) {
-    return Traits<S>::cvt(*(const S*)(base + off));
+__device__ __forceinline__ typename Traits<S>::T ldp(const LBM_GLOBAL char* __restrict__ base, uint32_t off) {
+    return Traits<S>::cvt(*(const LBM_GLOBAL S*)(base + off));
 }
 template <class S, bool NT = false>
-__device__ __forceinline__ void stp(char* __restrict__ base, uint32_t off, typename Traits<S>::T v) {
-    if (NT) __builtin_nontemporal_store(Traits<S>::store(v), (S*)(base + off));   // streaming store
-    else *(S*)(base + off) = Traits<S>::store(v);
+__device__ __forceinline__ void stp(LBM_GLOBAL char* __restrict__ base, uint32_t off, typename Traits<S>::T v) {
+    if (NT) __builtin_nontemporal_store(Traits<S>::store(v), (LBM_GLOBAL S*)(base + off));   // streaming store
+    else *(LBM_GLOBAL S*)(base + off) = Traits<S>::store(v);
 }
 
 // Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
@@ -267,19 +272,21 @@ struct __attribute__((aligned(8))) RowPair {
     uint32_t w1;
     int32_t p1;
 };
+// The same 16 bytes as loaded (8-byte aligned).
+typedef uint32_t RowWords __attribute__((ext_vector_type(4), aligned(8)));
 
 // Ordinary node: streaming and halfway bounce-back through the row table.
 // The nine row-table entries are loaded first and the population loads issued
 // after all of them (vector loads retire in order, so interleaving them would
 // serialize the rows).
 template <class S, bool PER, bool WALLS>
-__device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const StepArgs& a, int i,
+__device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a, int i,
                                             uint32_t w, typename Traits<S>::T (&f)[27],
                                             uint32_t& wallmask) {
     constexpr uint32_t SZ = sizeof(S);
     const uint32_t plane = (uint32_t)a.npad * SZ;
     const uint32_t ib = (uint32_t)i * SZ;
-    const char* rt = (const char*)a.rowtab;
+    const LBM_GLOBAL char* rt = (const LBM_GLOBAL char*)a.rowtab;
     const int x = (int)(w & 1023u);
     int y = 0, z = 0;
     uint32_t e0 = 0;
@@ -305,7 +312,11 @@ __device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const 
             if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
             e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
         }
-        rp[q] = *(const RowPair*)(rt + e * 8u);
+        const RowWords v = *(const LBM_GLOBAL RowWords*)(rt + e * 8u);
+        rp[q].w0 = v.x;
+        rp[q].p0 = (int32_t)v.y;
+        rp[q].w1 = v.z;
+        rp[q].p1 = (int32_t)v.w;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -337,8 +348,8 @@ __device__ __forceinline__ void gather_fast(const char* __restrict__ fin, const 
 // step (or the initial state): inlet f_a = f*_abar + add, outlet
 // f_a = -f*_abar + add (evaluated in FP64, rounded once).
 template <class S, bool MON>
-__device__ __forceinline__ void gather_special(const char* __restrict__ fin, const StepArgs& a,
-                                               const SpecialNode* __restrict__ sp,
+__device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a,
+                                               const LBM_GLOBAL SpecialNode* __restrict__ sp,
                                                typename Traits<S>::T (&f)[27], double (&F)[3],
                                                double& qin, double& qout) {
     using T = typename Traits<S>::T;
@@ -358,12 +369,14 @@ __device__ __forceinline__ void gather_special(const char* __restrict__ fin, con
     }
     if (lm) {
         int l = sp->link0;
+        const LBM_GLOBAL int32_t* meta = (const LBM_GLOBAL int32_t*)a.link_meta;
+        const LBM_GLOBAL double* add = (const LBM_GLOBAL double*)a.link_add;
 #pragma unroll
         for (int al = 0; al < 27; ++al) {
             if ((lm >> al) & 1u) {
-                const bool inlet = (a.link_meta[l] & 0xff) == LINK_INLET;
+                const bool inlet = (meta[l] & 0xff) == LINK_INLET;
                 const double own = (double)f[al];
-                const T vt = (T)((inlet ? own : -own) + a.link_add[l]);
+                const T vt = (T)((inlet ? own : -own) + add[l]);
                 f[al] = vt;
                 if (MON) {
                     const double q = (double)vt - own;
@@ -379,14 +392,16 @@ __device__ __forceinline__ void gather_special(const char* __restrict__ fin, con
 // Additive terms of a special node's open links for the step that streams the
 // populations of time t_next.  The inlet phase (cos, sin)(omega t_next) is read
 // from the device phase slots.
-__device__ __forceinline__ void update_links(const StepArgs& a, const SpecialNode* __restrict__ sp, double ux,
-                                          double uy, double uz, int64_t t_next) {
+__device__ __forceinline__ void update_links(const StepArgs& a, const LBM_GLOBAL SpecialNode* __restrict__ sp,
+                                          double ux, double uy, double uz, int64_t t_next) {
     const int l0 = sp->link0, nl = __popc(sp->linkmask);
-    const double cw = a.trig[2 * (t_next & 1)], sw = a.trig[2 * (t_next & 1) + 1];
+    const LBM_GLOBAL double* trig = (const LBM_GLOBAL double*)a.trig;
+    const double cw = trig[2 * (t_next & 1)], sw = trig[2 * (t_next & 1) + 1];
+    LBM_GLOBAL double* link_add = (LBM_GLOBAL double*)a.link_add;
     for (int l = l0; l < l0 + nl; ++l) {
-        const int meta = a.link_meta[l];
+        const int meta = ((const LBM_GLOBAL int32_t*)a.link_meta)[l];
         const int al = meta >> 8;
-        const double* cf = a.link_coef + LINK_COEFS * l;
+        const LBM_GLOBAL double* cf = (const LBM_GLOBAL double*)a.link_coef + LINK_COEFS * l;
         double add;
         if ((meta & 0xff) == LINK_INLET) {
             const double U = cf[0] + cf[1] * cw - cf[2] * sw;
@@ -409,7 +424,7 @@ __device__ __forceinline__ void update_links(const StepArgs& a, const SpecialNod
                              (c[2] == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
             add = 2.0 * (a.rho_out * even - w);
         }
-        a.link_add[l] = add;
+        link_add[l] = add;
     }
 }
 
@@ -491,19 +506,19 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
     const int i = lb * BS + threadIdx.x;
-    const char* __restrict__ fin = (const char*)a.fin;
-    char* __restrict__ fout = (char*)a.fout;
+    const LBM_GLOBAL char* __restrict__ fin = (const LBM_GLOBAL char*)a.fin;
+    LBM_GLOBAL char* __restrict__ fout = (LBM_GLOBAL char*)a.fout;
     double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < a.n) {
         T f[27];
         uint32_t wallmask = 0;
         double F[3] = {0.0, 0.0, 0.0}, qin = 0.0, qout = 0.0;
-        const uint32_t w = a.node[i];
-        const SpecialNode* sp = nullptr;
+        const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
+        const LBM_GLOBAL SpecialNode* sp = nullptr;
         if (!(w & SPECIAL_BIT)) {
             gather_fast<S, PER, MON>(fin, a, i, w, f, wallmask);
         } else {
-            sp = a.spec + (w & ~SPECIAL_BIT);
+            sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
             gather_special<S, MON>(fin, a, sp, f, F, qin, qout);
         }
         if (MON && wallmask) {

@@ -42,10 +42,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
         collide<T, false>(f, a, ux, uy, uz, drho, jx, jy, jz);
     const uint32_t w = a.node[i];
     if (w & SPECIAL_BIT) {
-        const SpecialNode* sp = a.spec + (w & ~SPECIAL_BIT);
+        const LBM_GLOBAL SpecialNode* sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
         if (sp->linkmask != 0u) update_links(a, sp, (double)ux, (double)uy, (double)uz, 0);
     }
-    char* fout = (char*)a.fout;
+    LBM_GLOBAL char* fout = (LBM_GLOBAL char*)a.fout;
     const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
     for (int al = 0; al < 27; ++al) stp<S>(fout, (uint32_t)al * plane + (uint32_t)i * SZ, f[al]);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, double* rho, doub
         u[2 * n + i] = avg[2 * n + i] * inv;
         return;
     }
-    const char* fin = (const char*)a.fin;
+    const LBM_GLOBAL char* fin = (const LBM_GLOBAL char*)a.fin;
     const uint32_t plane = (uint32_t)a.npad * SZ;
     double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BLOCK) void k_read_pop(StepArgs a, double* out) {
     constexpr uint32_t SZ = sizeof(S);
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= a.n) return;
-    const char* fin = (const char*)a.fin;
+    const LBM_GLOBAL char* fin = (const LBM_GLOBAL char*)a.fin;
     const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
     for (int al = 0; al < 27; ++al)
