@@ -111,6 +111,93 @@ __global__ __launch_bounds__(CONV_WAVES * 64) void k_conv_fwd(ConvArgs a) {
     }
 }
 
+// --- convolution forward on a brick staged in LDS -----------------------------------
+// A work-group computes a 16 x 4 x 4 (x, y, z) brick of output voxels (16
+// N-tiles of 16 voxels, four per wave).  The 18 x 6 x 6 input halo is first
+// copied to LDS with 8- or 16-byte loads (zeros outside the grid), so the B
+// fragments come from LDS; the weights (A) stay in global memory, where the
+// L1 serves them to every wave.  Requires d % 4 == 0, h % 4 == 0, w % 16 == 0.
+constexpr int BX = 16, BY = 4, BZ = 4;
+constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
+
+template <int CIN, int MT, bool F32OUT>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvArgs a) {
+    constexpr int PIECE = CIN * 2 >= 16 ? 16 : CIN * 2;   // bytes per staging load
+    constexpr int PPV = CIN * 2 / PIECE;                   // pieces per voxel
+    constexpr int NHALO = HZ * HY * HX;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[NHALO * CIN];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
+    int b = blockIdx.x;
+    const int bx = b % tx;
+    b /= tx;
+    const int by = b % ty;
+    b /= ty;
+    const int bz = b % tz;
+    const int s = b / tz;
+    const int xs = bx * BX - 1, ys = by * BY - 1, zs = bz * BZ - 1;   // halo origin
+    const int64_t V = (int64_t)a.d * a.h * a.w;
+    const int64_t sbase = (int64_t)s * V;
+    for (int idx = threadIdx.x; idx < NHALO * PPV; idx += 256) {
+        const int vox = idx / PPV, p = idx - vox * PPV;
+        const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+        const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
+        const bool in = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
+        const uint16_t* src = a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + p * (PIECE / 2);
+        uint16_t* dst = tile + vox * CIN + p * (PIECE / 2);
+        if constexpr (PIECE == 16) {
+            *(uint4*)dst = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+        } else {
+            *(uint2*)dst = in ? *(const uint2*)src : uint2{0u, 0u};
+        }
+    }
+    __syncthreads();
+    v4f acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    constexpr int K = 27 * CIN;
+    constexpr int KPAD = (K + 15) / 16 * 16;
+    // wave: output plane z = wave; N-tile t: output row y = t, x = r16
+#pragma unroll (CIN >= 32 ? 6 : 27)
+    for (int k0 = 0; k0 < KPAD; k0 += 16) {
+        const int k = k0 + 4 * q;
+        const int tap = k / CIN, ci = k - tap * CIN;
+        const bool kin = k < K;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+        v4s aw[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) aw[mt] = *(const v4s*)(a.wt + (int64_t)(mt * 16 + r16) * a.kpad + k);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int hv = ((wave + dz) * HY + (t + dy)) * HX + (r16 + dx);
+            const v4s bv = kin ? *(const v4s*)(tile + hv * CIN + ci) : v4s{0, 0, 0, 0};
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw[mt], bv, acc[mt][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t vox = sbase + ((int64_t)(zs + 1 + wave) * a.h + (ys + 1 + t)) * a.w + (xs + 1 + r16);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = mt * 16 + 4 * q + j;
+                if (co >= a.cout) continue;
+                float val = acc[mt][t][j] + (a.bias ? a.bias[co] : 0.0f);
+                if (a.relu) val = val > 0.0f ? val : 0.0f;
+                const int64_t idx = vox * a.ldy + a.cyo + co;
+                if (F32OUT) ((float*)a.y)[idx] = val;
+                else ((uint16_t*)a.y)[idx] = f2bf(val);
+            }
+        }
+    }
+}
+
 // --- weight gradient ------------------------------------------------------------
 // Block: one chunk of voxels (blockIdx.x) and 16 N-tiles (blockIdx.y), 4 per wave.
 template <int MT>
@@ -545,7 +632,25 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
+template <int CIN>
+hipError_t conv_lds(const ConvArgs& a, int mt, bool f32out, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)a.n * (a.d / BZ) * (a.h / BY) * (a.w / BX))), block(256);
+    if (mt == 1 && f32out) hipLaunchKernelGGL((k_conv_fwd_lds<CIN, 1, true>), grid, block, 0, st, a);
+    else if (mt == 1) hipLaunchKernelGGL((k_conv_fwd_lds<CIN, 1, false>), grid, block, 0, st, a);
+    else if (mt == 2 && f32out) hipLaunchKernelGGL((k_conv_fwd_lds<CIN, 2, true>), grid, block, 0, st, a);
+    else if (mt == 2) hipLaunchKernelGGL((k_conv_fwd_lds<CIN, 2, false>), grid, block, 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t conv_forward(const ConvArgs& a, int mt, bool f32out, hipStream_t st) {
+    // the brick kernel when the grid tiles into bricks and the staging loads
+    // stay aligned (16-byte pieces: row and channel offset multiples of 8
+    // channels; 8-byte pieces for 4 channels)
+    const bool bricks = a.d % BZ == 0 && a.h % BY == 0 && a.w % BX == 0 && a.kpad == (27 * a.cin + 15) / 16 * 16;
+    if (bricks && a.cin == 16 && a.ldx % 8 == 0 && a.cxo % 8 == 0) return conv_lds<16>(a, mt, f32out, st);
+    if (bricks && a.cin == 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) return conv_lds<32>(a, mt, f32out, st);
+    if (bricks && a.cin == 4 && a.ldx % 4 == 0 && a.cxo % 4 == 0) return conv_lds<4>(a, mt, f32out, st);
     const int64_t total = (int64_t)a.n * a.d * a.h * a.w;
     const unsigned grid = blocks_for(total, CONV_WAVES * CONV_VOX);
     const dim3 block(CONV_WAVES * 64);

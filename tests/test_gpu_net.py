@@ -29,13 +29,21 @@ def _per_sample(fn, *arrays):
     return [fn(*[a[s] for a in arrays]) for s in range(arrays[0].shape[0])]
 
 
+# Grids whose d and h are not multiples of 4 run the general kernel; the
+# others run the LDS brick kernel (both directions), for every input width.
 LAYER_CASES = [
     (4, 16, 1, (2, 3, 5, 16)),
-    (16, 16, 1, (1, 4, 4, 32)),
+    (16, 16, 1, (1, 3, 4, 32)),
     (16, 32, 1, (1, 5, 3, 16)),
     (32, 32, 0, (1, 3, 4, 16)),
     (32, 16, 1, (2, 2, 3, 16)),
     (16, 4, 0, (1, 3, 3, 48)),
+    (4, 16, 1, (2, 4, 4, 16)),
+    (16, 16, 1, (1, 4, 8, 32)),
+    (16, 32, 1, (1, 8, 4, 32)),
+    (32, 16, 0, (1, 4, 8, 16)),
+    (32, 32, 1, (2, 4, 4, 32)),
+    (16, 4, 1, (1, 4, 4, 48)),
 ]
 
 
