@@ -270,6 +270,123 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
         }
 }
 
+// --- weight gradient on bricks staged in LDS ---------------------------------------
+// Work-group (p, yb) accumulates, over the bricks p, p + P, p + 2P, ..., the
+// contribution of every voxel of the brick to N-tiles 28 yb .. 28 yb + 27 (7
+// per wave) and writes one partial per work-group.  Per brick the input halo
+// goes to LDS channel-major ([ci][halo voxel]) and the output gradient
+// transposed ([co][brick voxel]), so an A fragment (4 voxels of one channel)
+// is one 8-byte read and a B fragment 4 consecutive 2-byte reads.
+constexpr int WG_TPW = 7;   // N-tiles per wave
+
+template <int CIN, int MT>
+__global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts) {
+    constexpr int PIECE = CIN * 2 >= 16 ? 16 : CIN * 2;
+    constexpr int PPV = CIN * 2 / PIECE;
+    constexpr int NHALO = HZ * HY * HX;
+    constexpr int NB = BX * BY * BZ;   // voxels per brick (256)
+    constexpr int N = 27 * CIN;
+    __shared__ __attribute__((aligned(16))) uint16_t halo[CIN * NHALO];
+    __shared__ __attribute__((aligned(16))) uint16_t gy[MT * 16 * NB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
+    const int64_t nbricks = (int64_t)a.n * tx * ty * tz;
+    const int64_t V = (int64_t)a.d * a.h * a.w;
+    // rows of the output gradient beyond cout stay zero
+    for (int k = threadIdx.x; k < MT * 16 * NB; k += 256) gy[k] = 0;
+    // this wave's N-tiles: column n -> (tap, ci)
+    int tap_of[WG_TPW], ci_of[WG_TPW];
+    bool nin[WG_TPW];
+#pragma unroll
+    for (int t = 0; t < WG_TPW; ++t) {
+        const int n = ((int)blockIdx.y * 4 * WG_TPW + wave * WG_TPW + t) * 16 + r16;
+        nin[t] = n < N;
+        tap_of[t] = nin[t] ? n / CIN : 0;
+        ci_of[t] = nin[t] ? n - tap_of[t] * CIN : 0;
+    }
+    v4f acc[MT][WG_TPW];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < WG_TPW; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int64_t br = blockIdx.x; br < nbricks; br += nparts) {
+        int64_t b = br;
+        const int bx = (int)(b % tx);
+        b /= tx;
+        const int by = (int)(b % ty);
+        b /= ty;
+        const int bz = (int)(b % tz);
+        const int s = (int)(b / tz);
+        const int xs = bx * BX - 1, ys = by * BY - 1, zs = bz * BZ - 1;
+        const int64_t sbase = (int64_t)s * V;
+        __syncthreads();   // the previous brick's fragments have been read
+        for (int idx = threadIdx.x; idx < NHALO * PPV; idx += 256) {
+            const int vox = idx / PPV, p = idx - vox * PPV;
+            const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+            const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
+            const bool in = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
+            const uint16_t* src =
+                a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + p * (PIECE / 2);
+            uint16_t v[PIECE / 2];
+            if constexpr (PIECE == 16) {
+                const uint4 w4 = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+                const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[2 * e] = (uint16_t)(ww[e] & 0xffffu);
+                    v[2 * e + 1] = (uint16_t)(ww[e] >> 16);
+                }
+            } else {
+                const uint2 w2 = in ? *(const uint2*)src : uint2{0u, 0u};
+                v[0] = (uint16_t)(w2.x & 0xffffu);
+                v[1] = (uint16_t)(w2.x >> 16);
+                v[2] = (uint16_t)(w2.y & 0xffffu);
+                v[3] = (uint16_t)(w2.y >> 16);
+            }
+#pragma unroll
+            for (int e = 0; e < PIECE / 2; ++e) halo[(p * (PIECE / 2) + e) * NHALO + vox] = v[e];
+        }
+        for (int idx = threadIdx.x; idx < NB * a.cout; idx += 256) {
+            const int v = idx / a.cout, co = idx - v * a.cout;
+            const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
+            const int64_t g = sbase + ((int64_t)(zs + 1 + vz) * a.h + (ys + 1 + vy)) * a.w + (xs + 1 + vx);
+            gy[co * NB + v] = a.dy[g * a.ldy + co];
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k0 = 0; k0 < NB; k0 += 16) {
+            const int v0 = k0 + 4 * q;   // 4 voxels of one x row of the brick
+            const int vx = v0 % BX, vy = (v0 / BX) % BY, vz = v0 / (BX * BY);
+            v4s am[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) am[mt] = *(const v4s*)(gy + (mt * 16 + r16) * NB + v0);
+#pragma unroll
+            for (int t = 0; t < WG_TPW; ++t) {
+                const int tap = tap_of[t];
+                const int hv = ((vz + tap / 9) * HY + (vy + (tap / 3) % 3)) * HX + (vx + tap % 3);
+                const uint16_t* hp = halo + ci_of[t] * NHALO + hv;
+                v4s bn;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bn[j] = nin[t] ? (short)hp[j] : (short)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[mt], bn, acc[mt][t], 0, 0, 0);
+            }
+        }
+    }
+    float* part = a.part + (int64_t)blockIdx.x * a.mpad * a.npad;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < WG_TPW; ++t) {
+            const int n = ((int)blockIdx.y * 4 * WG_TPW + wave * WG_TPW + t) * 16 + r16;
+            if (n >= a.npad) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) part[(mt * 16 + 4 * q + j) * a.npad + n] = acc[mt][t][j];
+        }
+}
+
 // dW[co][n] = sum over chunks, only co < cout_param written.  A work-group
 // covers 32 outputs; each of its 8 thread groups sums every 8th chunk in
 // ascending order, then the 8 group sums are added in order (deterministic).
@@ -662,15 +779,44 @@ hipError_t conv_forward(const ConvArgs& a, int mt, bool f32out, hipStream_t st) 
     return hipGetLastError();
 }
 
+template <int CIN>
+hipError_t wgrad_lds(const WgradArgs& a, int mt, int nparts, hipStream_t st) {
+    const int ntiles = a.npad / 16;
+    const dim3 grid(nparts, (ntiles + 4 * WG_TPW - 1) / (4 * WG_TPW));
+    if (mt == 1) hipLaunchKernelGGL((k_conv_wgrad_lds<CIN, 1>), grid, dim3(256), 0, st, a, nparts);
+    else if (mt == 2) hipLaunchKernelGGL((k_conv_wgrad_lds<CIN, 2>), grid, dim3(256), 0, st, a, nparts);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st) {
     const int ntiles = a.npad / 16;
-    const dim3 grid(nchunks, (ntiles + 15) / 16);
-    if (mt == 1) hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(256), 0, st, a);
-    else if (mt == 2) hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(256), 0, st, a);
-    else return hipErrorInvalidValue;
+    // brick kernel: same tiling and alignment conditions as the forward one;
+    // at most nchunks partials (the size the caller's partial buffer holds)
+    const bool bricks = a.d % BZ == 0 && a.h % BY == 0 && a.w % BX == 0 && a.npad == (27 * a.cin + 15) / 16 * 16 &&
+                        a.cout <= 16 * mt;
+    const int64_t nbricks = (int64_t)a.n * (a.d / BZ) * (a.h / BY) * (a.w / BX);
+    const int nparts = (int)(nbricks < nchunks ? nbricks : nchunks);
+    hipError_t e;
+    int nred = nparts;   // partials the reduction sums
+    if (bricks && a.cin == 16 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
+        e = wgrad_lds<16>(a, mt, nparts, st);
+    } else if (bricks && a.cin == 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
+        e = wgrad_lds<32>(a, mt, nparts, st);
+    } else if (bricks && a.cin == 4 && a.ldx % 4 == 0 && a.cxo % 4 == 0) {
+        e = wgrad_lds<4>(a, mt, nparts, st);
+    } else {
+        const dim3 grid(nchunks, (ntiles + 15) / 16);
+        if (mt == 1) hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(256), 0, st, a);
+        else if (mt == 2) hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(256), 0, st, a);
+        else return hipErrorInvalidValue;
+        e = hipGetLastError();
+        nred = nchunks;
+    }
+    if (e != hipSuccess) return e;
     const int N = 27 * a.cin;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout_param * N, 32)), dim3(256), 0, st, a.part,
-                       nchunks, a.mpad, a.npad, cout_param, N, dw);
+                       nred, a.mpad, a.npad, cout_param, N, dw);
     return hipGetLastError();
 }
 
