@@ -152,10 +152,15 @@ int lbm_time(const lbm_domain* dom, int64_t* t);
 int lbm_moments(lbm_domain* dom, double* rho, double* u);
 
 /* Time averaging of u (FP64 accumulator in the attached memory).
- * op = LBM_AVG_RESET clears it, LBM_AVG_ACCUMULATE adds u(t), LBM_AVG_READ
- * writes the mean to u_avg (device double [3][n]; ESTATE if nothing was
- * accumulated).  Asynchronous. */
-enum { LBM_AVG_RESET = 0, LBM_AVG_ACCUMULATE = 1, LBM_AVG_READ = 2 };
+ * op = LBM_AVG_RESET clears it (and stops tracking), LBM_AVG_ACCUMULATE adds
+ * u(t) of the current state (a separate pass, u in FP64 from the stored
+ * populations), LBM_AVG_TRACK makes every following step add the velocity it
+ * computes for its collision (FP32 for the FP32/FP16/BF16 storage types, FP64
+ * for FP64; no extra launch or pass) until RESET or lbm_init_equilibrium,
+ * LBM_AVG_READ writes the mean of everything added since RESET to u_avg
+ * (device double [3][n]; ESTATE if nothing was added).  Tracking also applies
+ * to steps taken through a batch.  Asynchronous. */
+enum { LBM_AVG_RESET = 0, LBM_AVG_ACCUMULATE = 1, LBM_AVG_READ = 2, LBM_AVG_TRACK = 3 };
 int lbm_average(lbm_domain* dom, int op, double* u_avg);
 
 /* Monitors of the last step (host double[10]); synchronizes the stream.

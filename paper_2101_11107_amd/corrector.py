@@ -42,18 +42,18 @@ class Fields:
 
 
 def period_average(case, storage: str, steps: int | None = None, scale: float = 1.0 / U_SCALE) -> Fields:
-    """Run `case` from rest for one period (or `steps`), averaging u after
-    every step, then scatter the average onto the dense grid."""
+    """Run `case` from rest for one period (or `steps`), averaging u over
+    every step (inside the step kernel), then scatter the average onto the
+    dense grid."""
     import torch
     steps = case.period if steps is None else steps
     d = lbm.Domain(case, storage=storage)
     d.init()
     d.average(lbm.LBM_AVG_RESET)
+    d.average(lbm.LBM_AVG_TRACK)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        d.step(1)
-        d.average(lbm.LBM_AVG_ACCUMULATE)
+    d.step(steps)
     u_nodes = d.average(lbm.LBM_AVG_READ)
     d.stream.synchronize()
     seconds = time.perf_counter() - t0

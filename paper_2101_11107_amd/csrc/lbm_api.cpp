@@ -112,6 +112,7 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.cos_w = std::cos(d->omega);
     a.sin_w = std::sin(d->omega);
     a.partials = (double*)(base + d->off_part);
+    a.avg = d->avg_track ? (double*)(base + d->off_avg) : nullptr;
     a.tin = d->cur;
     a.n = (int)d->n;
     a.npad = d->npad;
@@ -572,6 +573,10 @@ int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
     d->initialized = true;
     d->monitored = false;
     d->avg_count = 0;
+    if (d->avg_track) {
+        d->avg_track = false;
+        d->drop_graphs();
+    }
     return LBM_OK;
 }
 
@@ -597,6 +602,7 @@ int lbm_step(lbm_domain* d, int nsteps) {
     rc = launch_steps_eager(d, left);
     if (rc) return rc;
     d->t += nsteps;
+    if (d->avg_track) d->avg_count += nsteps;
     if (nsteps > 0) {
         d->monitored = true;
         d->mon_blocks = d->nblocks;
@@ -628,6 +634,17 @@ int lbm_average(lbm_domain* d, int op, double* u_avg) {
         case LBM_AVG_RESET:
             HIP_TRY(lbm::launch_fill_zero(acc, (size_t)3 * d->n * sizeof(double), d->stream), "average reset");
             d->avg_count = 0;
+            if (d->avg_track) {
+                d->avg_track = false;
+                d->drop_graphs();
+            }
+            return LBM_OK;
+        case LBM_AVG_TRACK:
+            if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+            if (!d->avg_track) {
+                d->avg_track = true;
+                d->drop_graphs();
+            }
             return LBM_OK;
         case LBM_AVG_ACCUMULATE:
             if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");

@@ -84,6 +84,12 @@ int refresh_tables(lbm_batch* b) {
         HIP_TRY(hipStreamSynchronize(d->stream), "domain stream synchronize");
     }
     if (b->built_group_mb != b->cfg.group_mb) stale = true;
+    // any change of a domain's kernel arguments (parameters, boundary data,
+    // velocity tracking) since the tables were built
+    for (size_t k = 0; !stale && k < b->doms.size(); ++k) {
+        const lbm::StepArgs now = make_args(b->doms[k]);
+        stale = std::memcmp(&now, &b->args_host[k], sizeof now) != 0;
+    }
     if (!stale) return LBM_OK;
     const int bs = b->cfg.block;
     const size_t budget = b->cfg.group_mb > 0 ? ((size_t)b->cfg.group_mb << 20) : SIZE_MAX;
@@ -173,6 +179,7 @@ void advance_domains(lbm_batch* b, int nsteps) {
     for (lbm_domain* d : b->doms) {
         d->cur ^= (nsteps & 1);
         d->t += nsteps;
+        if (d->avg_track) d->avg_count += nsteps;
         d->monitored = true;
         d->mon_blocks = (int)((d->n + b->cfg.block - 1) / b->cfg.block);
     }

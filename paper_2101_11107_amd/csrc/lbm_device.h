@@ -537,6 +537,13 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         }
         T ux, uy, uz, drho, jx, jy, jz;
         collide<T, ONE>(f, a, ux, uy, uz, drho, jx, jy, jz);
+        if (a.avg != nullptr) {
+            // running sum of the velocity of every step (each node its own entries)
+            LBM_GLOBAL double* avg = (LBM_GLOBAL double*)a.avg;
+            avg[i] += (double)ux;
+            avg[a.n + i] += (double)uy;
+            avg[2 * a.n + i] += (double)uz;
+        }
         if (MON) {
             mon[0] = (double)drho;
             mon[1] = (double)jx;

@@ -78,6 +78,7 @@ struct lbm_domain {
     bool monitored = false;   // a monitored step ran since initialisation
     int mon_blocks = 0;       // monitor partials written by that step
     int64_t avg_count = 0;
+    bool avg_track = false;   // the step kernel adds u of every step to the accumulator
     double mon_host[lbm::MON_WORDS] = {0};
 
     // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer

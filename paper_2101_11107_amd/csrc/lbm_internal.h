@@ -62,6 +62,7 @@ struct StepArgs {
     int64_t* tcount;             // [2] time counters (read slot tin, write slot tin ^ 1)
     double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials
+    double* avg;                 // [3][n] FP64 velocity sums the step adds to, or null
     int tin;
     int n, npad, nx, ny, nz, W, periodic;
     int nblocks, blocks_per_xcd;

@@ -21,7 +21,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, 
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
 LBM_SOLID, LBM_FLUID, LBM_INLET, LBM_OUTLET = 0, 1, 2, 3
 LBM_PERIODIC_X, LBM_PERIODIC_Y, LBM_PERIODIC_Z = 1, 2, 4
-LBM_AVG_RESET, LBM_AVG_ACCUMULATE, LBM_AVG_READ = 0, 1, 2
+LBM_AVG_RESET, LBM_AVG_ACCUMULATE, LBM_AVG_READ, LBM_AVG_TRACK = 0, 1, 2, 3
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
 
@@ -372,7 +372,7 @@ class Domain:
         return f
 
     def average(self, op):
-        """op: LBM_AVG_RESET / LBM_AVG_ACCUMULATE, or LBM_AVG_READ (returns [3, n])."""
+        """op: LBM_AVG_RESET / LBM_AVG_ACCUMULATE / LBM_AVG_TRACK, or LBM_AVG_READ (returns [3, n])."""
         out = None
         if op == LBM_AVG_READ:
             out = self.torch.empty((3, self.n), dtype=self.torch.float64, device=self.device)

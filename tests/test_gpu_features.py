@@ -177,3 +177,64 @@ def test_step_before_init_is_rejected():
     with pytest.raises(lbm.LbmError):
         dom.monitors()
     dom.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_tracked_average_matches_separate_accumulation(storage, tol):
+    """Averaging inside the step kernel (LBM_AVG_TRACK, graphs allowed) equals
+    adding the moments after every single step (LBM_AVG_ACCUMULATE): the same
+    velocities, computed in the collision's precision instead of FP64."""
+    from paper_2101_11107_amd import lbm
+    print(f"case tracked average aneurysm128 {storage}", flush=True)
+    case = synth.aneurysm_case(128, seed=5)
+    steps = 67
+    a = lbm.Domain(case, storage=storage)
+    a.init()
+    a.average(lbm.LBM_AVG_RESET)
+    for _ in range(steps):
+        a.step(1)
+        a.average(lbm.LBM_AVG_ACCUMULATE)
+    ua = a.average(lbm.LBM_AVG_READ).cpu().numpy()
+    fa = a.populations().cpu().numpy()
+    a.close()
+    b = lbm.Domain(case, storage=storage)
+    b.init()
+    b.average(lbm.LBM_AVG_RESET)
+    b.average(lbm.LBM_AVG_TRACK)
+    b.step(steps)
+    ub = b.average(lbm.LBM_AVG_READ).cpu().numpy()
+    fb = b.populations().cpu().numpy()
+    b.close()
+    assert np.array_equal(fa, fb)          # tracking does not change the run
+    assert np.max(np.abs(ua - ub)) <= tol * np.max(np.abs(ua))
+
+
+def test_tracked_average_through_batch_equals_solo():
+    from paper_2101_11107_amd import lbm
+    print("case tracked average batch f16s", flush=True)
+    cases = [synth.aneurysm_case(64, seed=s) for s in (1, 2)]
+    doms = [lbm.Domain(c, storage="f16s") for c in cases]
+    for d in doms:
+        d.init()
+    b = lbm.Batch(doms)
+    b.step(8)                                  # tables built without tracking
+    for d in doms:
+        d.average(lbm.LBM_AVG_RESET)
+        d.average(lbm.LBM_AVG_TRACK)
+    b.step(40)                                 # the batch sees the tracking change
+    got = [d.average(lbm.LBM_AVG_READ).cpu().numpy() for d in doms]
+    b.close()
+    for d in doms:
+        d.close()
+    # the batch run is 8 steps ahead of the solo runs: compare with solo runs of 48
+    ref = []
+    for c in cases:
+        d = lbm.Domain(c, storage="f16s")
+        d.init()
+        d.step(8)
+        d.average(lbm.LBM_AVG_TRACK)
+        d.step(40)
+        ref.append(d.average(lbm.LBM_AVG_READ).cpu().numpy())
+        d.close()
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
