@@ -28,6 +28,7 @@ namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     const __bf16 h = (__bf16)f;                // round to nearest even
@@ -159,24 +160,52 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvArgs a) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
     constexpr int K = 27 * CIN;
-    constexpr int KPAD = (K + 15) / 16 * 16;
     // wave: output plane z = wave; N-tile t: output row y = t, x = r16
-#pragma unroll (CIN >= 32 ? 6 : 27)
-    for (int k0 = 0; k0 < KPAD; k0 += 16) {
-        const int k = k0 + 4 * q;
-        const int tap = k / CIN, ci = k - tap * CIN;
-        const bool kin = k < K;
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
-        v4s aw[MT];
+    if constexpr (CIN % 8 == 0) {
+        // v_mfma_f32_16x16x32_bf16: a lane holds 8 consecutive K, i.e. 8
+        // channels of one tap (one 16-byte read each for A and B)
+        constexpr int KP32 = (K + 31) / 32 * 32;
+#pragma unroll (CIN >= 32 ? 3 : 14)
+        for (int k0 = 0; k0 < KP32; k0 += 32) {
+            const int k = k0 + 8 * q;
+            const int tap = k / CIN, ci = k - tap * CIN;
+            const bool kin = k < K;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+            v8b aw[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) aw[mt] = *(const v4s*)(a.wt + (int64_t)(mt * 16 + r16) * a.kpad + k);
+            for (int mt = 0; mt < MT; ++mt) {
+                const v8b z = {};
+                aw[mt] = kin ? *(const v8b*)(a.wt + (int64_t)(mt * 16 + r16) * a.kpad + k) : z;
+            }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int hv = ((wave + dz) * HY + (t + dy)) * HX + (r16 + dx);
-            const v4s bv = kin ? *(const v4s*)(tile + hv * CIN + ci) : v4s{0, 0, 0, 0};
+            for (int t = 0; t < 4; ++t) {
+                const int hv = ((wave + dz) * HY + (t + dy)) * HX + (r16 + dx);
+                const v8b z = {};
+                const v8b bv = kin ? *(const v8b*)(tile + hv * CIN + ci) : z;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw[mt], bv, acc[mt][t], 0, 0, 0);
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[mt], bv, acc[mt][t], 0, 0, 0);
+            }
+        }
+    } else {
+        constexpr int KPAD = (K + 15) / 16 * 16;
+#pragma unroll
+        for (int k0 = 0; k0 < KPAD; k0 += 16) {
+            const int k = k0 + 4 * q;
+            const int tap = k / CIN, ci = k - tap * CIN;
+            const bool kin = k < K;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+            v4s aw[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) aw[mt] = *(const v4s*)(a.wt + (int64_t)(mt * 16 + r16) * a.kpad + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int hv = ((wave + dz) * HY + (t + dy)) * HX + (r16 + dx);
+                const v4s bv = kin ? *(const v4s*)(tile + hv * CIN + ci) : v4s{0, 0, 0, 0};
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw[mt], bv, acc[mt][t], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
