@@ -38,38 +38,58 @@ __global__ __launch_bounds__(BS) void k_batch_step(BatchArgs b, int step) {
     batch_item<S, MON, ONE, NT, BS>(b, item, step);
 }
 
-// Device-wide barrier (sense by generation count).  Returns false if the wait
-// exceeded its bound; then the error flag is set and every work-group leaves.
-__device__ bool grid_barrier(const BatchArgs& b) {
-    __shared__ int ok;
+// Device-wide barrier for epoch e (1, 2, ... within one launch; the host clears
+// the barrier words before every persistent launch).  Work-group g publishes
+// its arrival in its own word (no contention); work-group 0 waits for every
+// arrival, then publishes the release; the others wait for the release.
+// Every wait is bounded: on a timeout the error flag is set and every
+// work-group leaves.  Layout: barrier[0] release epoch, barrier[64 + g] arrival
+// of work-group g (at most MAX_PERSISTENT_GROUPS).
+__device__ bool grid_barrier(const BatchArgs& b, unsigned epoch) {
+    __shared__ int bad;
+    unsigned* release = b.barrier;
+    unsigned* arrive = b.barrier + 64;
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int good = 1;
-        unsigned* count = b.barrier;
-        unsigned* gen = b.barrier + 1;
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();   // release this work-group's stores
-        const unsigned arrived = atomicAdd(count, 1u);
-        if (arrived == gridDim.x - 1) {
-            atomicExch(count, 0u);
-            __threadfence();
-            atomicAdd(gen, 1u);
-        } else {
+        __threadfence();   // this work-group's stores happen before its arrival
+        __hip_atomic_store(arrive + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        for (unsigned k = threadIdx.x; k < gridDim.x && !bad; k += blockDim.x) {
             unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(arrive + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > SPIN_LIMIT || __hip_atomic_load(b.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    atomicExch(b.error, 1);
-                    good = 0;
+                    bad = 1;
                     break;
                 }
             }
         }
+        __threadfence();   // the observed work-groups' stores happen before the release
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (bad) atomicExch(b.error, 1);
+            __threadfence();
+            __hip_atomic_store(release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT || __hip_atomic_load(b.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicExch(b.error, 1);
+                bad = 1;
+                break;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
         __threadfence();   // acquire the other work-groups' stores
-        ok = good;
+        if (__hip_atomic_load(b.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) bad = 1;
     }
     __syncthreads();
-    return ok != 0;
+    return bad == 0;
 }
 
 // Steps step0 .. step0 + nsteps - 1 without monitors (the monitored last step
@@ -79,7 +99,7 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs b, int step0,
     for (int s = 0; s < nsteps; ++s) {
         for (int item = blockIdx.x; item < b.nitems; item += gridDim.x)
             batch_item<S, false, ONE, NT, BS>(b, item, step0 + s);
-        if (s + 1 < nsteps && !grid_barrier(b)) return;
+        if (s + 1 < nsteps && !grid_barrier(b, (unsigned)(s + 1))) return;
     }
 }
 
@@ -162,6 +182,7 @@ hipError_t persistent_s(bool one, const BatchArgs& b, const BatchConfig& c, int 
     // never more work-groups than fit at once: the barrier needs them all resident
     if (grid <= 0 || grid > cap) grid = cap;
     if (grid > b.nitems) grid = b.nitems;
+    if (grid > MAX_PERSISTENT_GROUPS) grid = MAX_PERSISTENT_GROUPS;
     return one ? persistent_one<S, true>(b, c, grid, step0, nsteps, st)
                : persistent_one<S, false>(b, c, grid, step0, nsteps, st);
 }

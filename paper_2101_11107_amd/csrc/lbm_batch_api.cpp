@@ -137,6 +137,9 @@ int refresh_tables(lbm_batch* b) {
 int enqueue_steps(lbm_batch* b, int g, int nsteps) {
     const lbm::BatchArgs a = batch_args(b, g);
     if (b->cfg.mode == 1 && nsteps > 1) {
+        // barrier epochs restart at 1 in every launch
+        HIP_TRY(lbm::launch_fill_zero(a.barrier, lbm::BARRIER_WORDS * sizeof(unsigned), b->stream),
+                "barrier reset");
         HIP_TRY(lbm::launch_batch_persistent(b->storage, b->rates_one, a, b->cfg, 0, nsteps - 1, b->stream),
                 "persistent batch kernel");
         HIP_TRY(lbm::launch_batch_step(b->storage, b->rates_one, a, b->cfg, nsteps - 1, true, b->stream),
@@ -263,7 +266,7 @@ int lbm_batch_create(lbm_domain* const* doms, int n, void* hip_stream, lbm_batch
         return fail(LBM_EINVAL, "too many domains in one batch");
     }
     b->off_items = take((size_t)max_items * sizeof(int));
-    b->off_barrier = take(2 * sizeof(unsigned));
+    b->off_barrier = take(lbm::BARRIER_WORDS * sizeof(unsigned));
     b->off_error = take(sizeof(int));
     b->dev_bytes = off;
     *out = b;

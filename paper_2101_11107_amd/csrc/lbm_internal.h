@@ -86,13 +86,15 @@ struct StepVariant {
 // (item_map[k] & ITEM_BLOCK_MASK) of domain (item_map[k] >> ITEM_DOMAIN_SHIFT);
 // doms[d] holds the domain's arguments for its buffer parity at the start of
 // the launch sequence (odd steps swap the buffers and the time slot).
+constexpr int MAX_PERSISTENT_GROUPS = 4096;              // work-groups of one persistent launch
+constexpr int BARRIER_WORDS = 64 + MAX_PERSISTENT_GROUPS;   // release word, padding, arrivals
 constexpr int ITEM_DOMAIN_SHIFT = 20;
 constexpr int ITEM_BLOCK_MASK = (1 << ITEM_DOMAIN_SHIFT) - 1;
 struct BatchArgs {
     const StepArgs* doms;        // [ndom]
     const int* item_map;         // [nitems]
     int ndom, nitems, items_per_xcd;
-    unsigned* barrier;           // [2] arrival count and generation (persistent mode)
+    unsigned* barrier;           // [BARRIER_WORDS] device-wide barrier words (persistent mode)
     int* error;                  // set when a device-wide barrier wait exceeded its bound
 };
 
