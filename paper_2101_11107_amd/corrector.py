@@ -323,7 +323,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train and score the coarse-to-fine corrector")
     ap.add_argument("--train", type=int, default=48, help="training seeds 0..train-1")
     ap.add_argument("--test", type=int, default=16, help="held-out seeds after the training seeds")
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--iters", type=int, default=6000)
     ap.add_argument("--out", default=None, help="write the summary (JSON) and parameters (.npy) here")
     a = ap.parse_args(argv)
     cfg = TrainConfig(iters=a.iters, log_every=max(1, a.iters // 10))
