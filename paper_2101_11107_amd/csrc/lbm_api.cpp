@@ -315,19 +315,23 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
         d->stream = (hipStream_t)hip_stream;
         d->n = nfluid;
         d->npad = (int)npad;
-        d->W = ((nx + 1) >> 5) + 2;
+        d->W = (nx + lbm::ROW_SPAN - 1) / lbm::ROW_SPAN;
         d->rows = (ny + 2) * (nz + 2);
         d->nblocks = (int)(npad / lbm::BLOCK);
         d->blocks_per_xcd = (d->nblocks + 7) / 8;
 
-        // row table: fluid bitmap (bit x + 1 of row (y, z), one empty row ring
-        // around the box) and the count of fluid nodes before each word
+        // row table: overlapping fluid bitmaps of each row (one empty row ring
+        // around the box) and the list index of each entry's first cell
         d->rowtab.assign((size_t)d->rows * d->W, lbm::RowEntry{0u, 0});
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y) {
                 const size_t r = (size_t)d->row_of(y, z) * d->W;
-                for (int x = 0; x < nx; ++x)
-                    if (mask[d->cell(x, y, z)] == LBM_FLUID) d->rowtab[r + ((x + 1) >> 5)].bits |= 1u << ((x + 1) & 31);
+                for (int x = 0; x < nx; ++x) {
+                    if (mask[d->cell(x, y, z)] != LBM_FLUID) continue;
+                    const int k = (x + 1) / lbm::ROW_SPAN, j = x + 1 - k * lbm::ROW_SPAN;
+                    if (k < d->W) d->rowtab[r + k].bits |= 1u << j;
+                    if (j <= 1 && k >= 1) d->rowtab[r + k - 1].bits |= 1u << (j + lbm::ROW_SPAN);
+                }
             }
         // List order: rows grouped in tiles of ROW_TILE x ROW_TILE rows of the
         // (y, z) plane, x fastest inside a row.  Neighbouring rows then sit close
@@ -340,12 +344,15 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                 for (int z = tz; z < std::min(nz, tz + ROW_TILE); ++z)
                     for (int y = ty; y < std::min(ny, ty + ROW_TILE); ++y) order.push_back(d->row_of(y, z));
         int64_t cnt = 0;
-        for (int r : order)
-            for (int wd = 0; wd < d->W; ++wd) {
-                lbm::RowEntry& e = d->rowtab[(size_t)r * d->W + wd];
-                e.prefix = (int32_t)cnt;
-                cnt += __builtin_popcount(e.bits);
+        for (int r : order) {
+            const int z = r / (ny + 2) - 1, y = r % (ny + 2) - 1;
+            int x = 0;
+            for (int k = 0; k < d->W; ++k) {
+                for (; x < std::min(nx, k * lbm::ROW_SPAN - 1); ++x) cnt += mask[d->cell(x, y, z)] == LBM_FLUID;
+                d->rowtab[(size_t)r * d->W + k].prefix = (int32_t)cnt;
             }
+            for (; x < nx; ++x) cnt += mask[d->cell(x, y, z)] == LBM_FLUID;
+        }
         if (cnt != nfluid) return fail(LBM_EINVAL, "internal: bitmap count mismatch");
         if ((int64_t)d->rows * d->W >= ((int64_t)1 << 29)) return fail(LBM_EINVAL, "box too large for the row table");
 

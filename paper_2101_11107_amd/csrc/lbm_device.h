@@ -266,14 +266,8 @@ __device__ __forceinline__ void collide_rates_one(T (&f)[27], const T (&S0)[9], 
 }
 
 // --- gather of the incoming populations -------------------------------------------
-// Bitmap word of a source row at the node's x, its prefix count, and the next
-// bitmap word (12 bytes of two adjacent row-table entries; the second prefix
-// is not needed, and loading only 12 bytes is measurably faster).
-struct RowPair {
-    uint32_t w0;
-    int32_t p0;
-    uint32_t w1;
-};
+// Row-table entry of a source row at the node's x (one 8-byte load).
+typedef uint32_t RowWord2 __attribute__((ext_vector_type(2)));
 
 // Ordinary node: streaming and halfway bounce-back through the row table.
 // The nine row-table entries are loaded first and the population loads issued
@@ -290,16 +284,17 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
     const int x = (int)(w & 1023u);
     int y = 0, z = 0;
     uint32_t e0 = 0;
+    const uint32_t kw = ((uint32_t)x * 2185u) >> 16;   // x / ROW_SPAN (exact for x < 1024)
     if (!PER) {
-        e0 = (w >> 10) * (uint32_t)a.W + (uint32_t)(x >> 5);
+        e0 = (w >> 10) * (uint32_t)a.W + kw;
     } else {
         y = (int)((w >> 10) & 1023u);
         z = (int)((w >> 20) & 1023u);
     }
-    const uint32_t sh = (uint32_t)x & 31u;
-    const uint32_t low = (uint32_t)((2ull << sh) - 1ull);
+    const uint32_t sh = (uint32_t)x - (uint32_t)ROW_SPAN * kw;   // bit of cell x - 1
+    const uint32_t low = (2u << sh) - 1u;                         // cells 30k - 1 .. x - 1
     const int rowlen = a.ny + 2;
-    RowPair rp[9];
+    RowWord2 rp[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ky = q % 3, kz = q / 3;
@@ -310,20 +305,17 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
             int ys = y - (ky - 1), zs = z - (kz - 1);
             if (a.periodic & 2) ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
             if (a.periodic & 4) zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
-            e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + (uint32_t)(x >> 5);
+            e = (uint32_t)((zs + 1) * rowlen + (ys + 1)) * (uint32_t)a.W + kw;
         }
-        const LBM_GLOBAL uint32_t* ve = (const LBM_GLOBAL uint32_t*)(rt + e * 8u);
-        rp[q].w0 = ve[0];
-        rp[q].p0 = (int32_t)ve[1];
-        rp[q].w1 = ve[2];
+        rp[q] = *(const LBM_GLOBAL RowWord2*)(rt + e * 8u);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ky = q % 3, kz = q / 3;
         // bits of cells x - 1, x, x + 1 of this row
-        const uint32_t win = __builtin_amdgcn_alignbit(rp[q].w1, rp[q].w0, sh);
-        const int base = (q == 4) ? i : rp[q].p0 + (int)__popc(rp[q].w0 & low);
+        const uint32_t win = rp[q].x >> sh;
+        const int base = (q == 4) ? i : (int)rp[q].y + (int)__popc(rp[q].x & low);
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
             const int al = 9 * kz + 3 * ky + kx;

@@ -96,11 +96,11 @@ struct lbm_domain {
     int64_t cell(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
     int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
     // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
+    // of the entry's cells 30k - 1 .. x - 1
     int32_t index_of(int x, int y, int z) const {
-        const int p = x + 1;
-        const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + (p >> 5)];
-        const uint32_t low = (p & 31) ? ((1u << (p & 31)) - 1u) : 0u;
-        return e.prefix + __builtin_popcount(e.bits & low);
+        const int k = x / lbm::ROW_SPAN, r = x - k * lbm::ROW_SPAN;
+        const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + k];
+        return e.prefix + __builtin_popcount(e.bits & ((2u << r) - 1u));
     }
     bool rates_one() const { return s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0; }
     bool periodic_yz() const { return (periodic & 6u) != 0; }

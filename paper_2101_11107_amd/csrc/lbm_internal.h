@@ -18,8 +18,12 @@ constexpr int MAX_DIM = 1023;
 constexpr int BLOCK = 256;            // threads per work-group of the step kernel
 constexpr int MON_WORDS = 10;         // doubles per work-group monitor partial
 
-// Row table entry: fluid bitmap word of a row (bit x + 1 for cell x) and the
-// number of fluid nodes before that word in list (x-fastest) order.
+// Row table entry k of a row: fluid bits of the 32 cells 30k - 1 .. 30k + 30
+// (bit j for cell 30k - 1 + j; neighbouring entries overlap by two cells, so
+// the cells x - 1, x, x + 1 of any x in 30k .. 30k + 29 sit in entry k) and the
+// list index of the row's first fluid cell at or after 30k - 1 (the number
+// of fluid nodes before it in list order).
+constexpr int ROW_SPAN = 30;          // cells per row-table entry
 struct alignas(8) RowEntry {
     uint32_t bits;
     int32_t prefix;
