@@ -138,27 +138,30 @@ def batch_bench(torch, lbm, steps, storage="f16s"):
 
 
 def corrector_bench():
-    """Reduced protocol of the learned corrector: 12 training geometries, 1500
-    Adam steps, 3 held-out geometries scored against their FP64 fine runs."""
+    """The learned corrector's protocol: 48 training geometries, 6000 Adam
+    steps, 16 held-out geometries scored against their FP64 fine runs, with
+    the fallback thresholds calibrated on the training geometries."""
     import numpy as np
     from paper_2101_11107_amd import corrector as C
-    from synth import aneurysm_case
-    train = [C.make_pair(s) for s in range(12)]
-    test = [C.make_pair(s) for s in (48, 49, 50)]
-    tr = C.train(train, C.TrainConfig(iters=1500, log_every=1500), log=None)
-    ev = [C.evaluate(tr.params, p) for p in test]
-    fine_f32 = C.period_average(aneurysm_case(256, 48), "f32").seconds
-    return {"workload": "corrector_aneurysm128_to_256", "train_geometries": 12, "held_out_geometries": 3,
-            "adam_steps": tr.iters, "train_seconds": round(tr.seconds, 2),
-            "ms_per_train_step": round(1e3 * tr.seconds / tr.iters, 2),
-            "u_rel_l2_net_vs_f64_fine": round(float(np.mean([e.l2_net for e in ev])), 5),
-            "u_rel_l2_trilinear_vs_f64_fine": round(float(np.mean([e.l2_tri for e in ev])), 5),
-            "similarity_index_net": round(float(np.mean([e.si_net for e in ev])), 5),
-            "similarity_index_trilinear": round(float(np.mean([e.si_tri for e in ev])), 5),
-            "coarse_run_s": round(float(np.mean([e.coarse_seconds for e in ev])), 4),
-            "inference_s": round(float(np.mean([e.infer_seconds for e in ev])), 4),
-            "fine_run_f32_s": round(fine_f32, 4),
-            "fine_run_f64_s": round(float(np.mean([e.fine_seconds for e in ev])), 4)}
+    res = C.run_protocol(range(48), range(48, 64), C.TrainConfig(iters=6000, log_every=1500),
+                         log=lambda m: note(f"corrector: {m}"))
+    l2n, l2t = np.array(res["l2_net"]), np.array(res["l2_tri"])
+    sin, sit = np.array(res["si_net"]), np.array(res["si_tri"])
+    return {"workload": "corrector_aneurysm128_to_256", "train_geometries": 48, "held_out_geometries": 16,
+            "adam_steps": res["train_iters"], "train_seconds": round(res["train_seconds"], 2),
+            "ms_per_train_step": round(1e3 * res["train_seconds"] / res["train_iters"], 2),
+            "data_seconds": round(res["data_seconds"], 2),
+            "u_rel_l2_net_vs_f64_fine": round(float(l2n.mean()), 5),
+            "u_rel_l2_trilinear_vs_f64_fine": round(float(l2t.mean()), 5),
+            "similarity_index_net": round(float(sin.mean()), 5),
+            "similarity_index_trilinear": round(float(sit.mean()), 5),
+            "held_out_better_on_both": int(np.sum((l2n < l2t) & (sin > sit))),
+            "fallback_rate": res["fallback_rate"],
+            "coarse_run_s": round(res["coarse_seconds"], 4),
+            "inference_s": round(res["infer_seconds"], 4),
+            "fine_run_f32_s": round(res["fine_seconds_f32"], 4),
+            "fine_run_f64_s": round(res["fine_seconds_f64"], 4),
+            "speedup_vs_fine_f32": round(res["speedup_vs_fine_f32"], 2)}
 
 
 def roofline(n, ms_per_step, storage, traffic):
@@ -191,6 +194,11 @@ def cpu_baseline(case, budget_s):
 def rel_l2(u, ref):
     import numpy as np
     return float(np.sqrt(((u - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def note(msg):
+    """Progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -230,6 +238,7 @@ def main():
     size = 256 if workload == "aneurysm256" else 512
     case = synth.aneurysm_case(size, seed=0)
     main_run = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=not args.no_extra)
+    note(f"{workload} {args.storage}: {main_run['mlups']:.1f} MLUPS, {main_run['ms_per_step'] * 1e3:.2f} us per step")
     traffic = read_traffic(args.storage, workload)
     line = {
         "metric": "fluid-node MLUPS (D3Q27 CHM-MRT fused stream-collide step)",
@@ -266,6 +275,7 @@ def main():
             cs = case if wl == workload else synth.aneurysm_case(sz, seed=0)
             warm, steps_x = (args.warmup, args.steps) if wl == workload else (100, 1000)
             ref = run_form(torch, lbm, cs, "f64", warm, steps_x, want_u=True)
+            note(f"{wl} f64: {ref['mlups']:.1f} MLUPS")
             if wl == workload:
                 line["f32_velocity_rel_l2_vs_f64" if args.storage == "f32" else
                      f"{args.storage}_velocity_rel_l2_vs_f64"] = rel_l2(main_run["u"], ref["u"])
@@ -273,6 +283,8 @@ def main():
                 if wl == workload and st == args.storage:
                     continue
                 r = ref if st == "f64" else run_form(torch, lbm, cs, st, warm, steps_x, want_u=True)
+                if st != "f64":
+                    note(f"{wl} {st}: {r['mlups']:.1f} MLUPS")
                 rf = roofline(r["n"], r["ms_per_step"], st, read_traffic(st, wl))
                 row = {"workload": wl, "storage": st, "fluid_nodes": r["n"], "mlups": round(r["mlups"], 1),
                        "achieved_GBs": rf["achieved"], "roofline_frac": rf["frac"], "traffic": rf["traffic"],
@@ -285,12 +297,15 @@ def main():
                 also.append(row)
             del ref
         also.append(batch_bench(torch, lbm, 480))
+        note(f"batch: {also[-1]['batched_mlups']:.1f} MLUPS batched")
         if not args.no_corrector:
             also.append(corrector_bench())
+            note("corrector protocol done")
         line["also"] = also
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        note(f"cpu baseline: {line['cpu_baseline']['value']} MLUPS")
     print(json.dumps(line), flush=True)
 
 

@@ -38,6 +38,21 @@ def test_tiny_random_cases_f32_population_parity(seed):
     assert np.max(np.abs(f - ref)) < 1e-5 * np.max(np.abs(ref))
 
 
+# seeds whose random rates and inlet stay stable for 12 steps at these widths
+@pytest.mark.parametrize("seed,nx", [(3, 30), (1, 31), (10, 61), (3, 62), (0, 91)])
+def test_rows_across_row_table_entries_f64(seed, nx):
+    """Rows longer than one row-table entry (30 cells): random walls, ghost
+    cells and periodic axes (all, none, z only, x and y) on both sides of every
+    entry boundary, with rows ending exactly at one or one or two cells past."""
+    print(f"case rows{seed} nx={nx} f64", flush=True)
+    case = synth.random_tiny_case(seed, nx=nx, ny=5, nz=4)
+    dom, f = gpu_run(case, "f64", 12)
+    dom.close()
+    _, ref, _, _ = oracle_post(case, 12)
+    assert f.shape == ref.shape
+    assert np.max(np.abs(f - ref)) < 1e-13
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_pipe_poiseuille_2000_steps(storage, tol):
     """Config 1: 64x24x24 periodic pipe, R = 10, g = 1e-6, tau = 0.8, 2000 steps."""
