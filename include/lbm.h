@@ -94,6 +94,37 @@ const char* lbm_last_error(void);
 int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
                       int storage, void* hip_stream, lbm_domain** out);
 
+/* Curved walls by interpolated bounce-back (Sec. 2.1.4, Eq. (9)-(10), the
+ * linear interpolation of Bouzidi et al. that the paper cites).  The same as
+ * lbm_create_domain, plus wall distances for nwall links: link k is the fluid
+ * cell (x, y, z) = links[4k .. 4k+2] and the direction alpha = links[4k+3]
+ * (D3Q27 index, not 13) towards a wall, i.e. the cell x + c_alpha is SOLID or
+ * lies outside a non-periodic box (lbm_wall_links lists them); q[k] in (0, 1]
+ * is the distance from the node to the wall along the link in units of
+ * |c_alpha|.  With abar the opposite direction, the population returning to
+ * x is
+ *   q <  1/2: 2q f*_alpha(x, t) + (1 - 2q) f*_alpha(x - c_alpha, t),
+ *   q >= 1/2: f*_alpha(x, t) / (2q) + (2q - 1) / (2q) f*_abar(x, t),
+ * both halfway bounce-back at q = 1/2; for q < 1/2 the node x - c_alpha must
+ * be fluid, otherwise that link keeps halfway bounce-back.  The wall force of
+ * a curved link is (f*_alpha(x, t) + f_abar(x, t + 1)) c_alpha.  Links not
+ * listed keep halfway bounce-back.  The arrays are host memory, read during
+ * the call.  Nodes with curved links take the explicit-offset path of the
+ * step (slower than the bitmap path).  Errors: EINVAL for a link that is out
+ * of range, does not start at a fluid cell or end at a wall, is listed twice,
+ * or has q outside (0, 1]; otherwise as lbm_create_domain. */
+int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
+                             int storage, const int32_t* links, const double* q, int64_t nwall,
+                             void* hip_stream, lbm_domain** out);
+
+/* Wall links of a mask (same layout and periodic rules as lbm_create_domain):
+ * every pair of a FLUID cell and a direction alpha whose cell x + c_alpha is
+ * SOLID or outside a non-periodic box, in x-fastest cell order, then alpha.
+ * links: host int32 [count][4] = (x, y, z, alpha), or NULL to get the count
+ * only.  *count receives the number of links.  EINVAL for bad sizes or flags. */
+int lbm_wall_links(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
+                   int32_t* links, int64_t* count);
+
 /* Device bytes the caller must provide to lbm_attach_device. */
 int lbm_device_bytes(const lbm_domain* dom, size_t* bytes);
 

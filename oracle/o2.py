@@ -49,9 +49,9 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.o2_collide.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_int]
-        lib.o2_stream.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, ctypes.c_int]
+        lib.o2_stream.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, ctypes.c_int, P]
         lib.o2_run.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_int, P,
-                               ctypes.c_int]
+                               ctypes.c_int, P]
         lib.o2_mass_momentum.argtypes = [ctypes.c_int64, P, P]
         _lib = lib
     return _lib
@@ -73,9 +73,14 @@ class O2Sim:
     Nodes are the fluid cells in x-fastest order (``coords[n] = (x, y, z)``).
     ``f`` holds the pre-collision populations f(t) [N, 27]; after a step,
     ``fpost`` holds f*(t-1) and ``u`` the velocities of that collision.
+
+    ``wall_q``: optional wall distances for curved walls, a mapping
+    (x, y, z, a) -> q for links from fluid node (x, y, z) in direction a whose
+    neighbour x + c_a is a wall (Eq. (9)-(10)); other wall links keep halfway
+    bounce-back.
     """
 
-    def __init__(self, case, nthreads: int = 0, rates5=None, g_time=None):
+    def __init__(self, case, nthreads: int = 0, rates5=None, g_time=None, wall_q=None):
         self.case = case
         self.lib = _load()
         nz, ny, nx = case.mask.shape
@@ -107,6 +112,14 @@ class O2Sim:
                                              float(case.inlet.G1), float(case.inlet.omega))
         c.nu = (case.tau - 0.5) / 3.0
         self.c = c
+        self.wq = None
+        if wall_q is not None:
+            self.wq = np.full((self.n, 27), 0.5)
+            for (x, y, z, a), q in wall_q.items():
+                k = self.idx[(z * ny + y) * nx + x]
+                if k < 0:
+                    raise ValueError(f"wall link at a non-fluid cell {(x, y, z)}")
+                self.wq[k, a] = float(q)
         self.f = np.tile(_weights()[None, :], (self.n, 1))
         self.fpost = np.zeros((self.n, 27))
         self.u = np.zeros((self.n, 3))
@@ -116,11 +129,14 @@ class O2Sim:
     def run(self, nsteps: int) -> np.ndarray:
         rc = self.lib.o2_run(ctypes.byref(self.c), _ptr(self.mask), _ptr(self.coords), _ptr(self.idx),
                              self.n, _ptr(self.f), _ptr(self.fpost), _ptr(self.u), self.t,
-                             int(nsteps), _ptr(self.monitors), self.nthreads)
+                             int(nsteps), _ptr(self.monitors), self.nthreads, self._wq())
         if rc != 0:
             raise RuntimeError("o2_run failed (inlet cells without inlet parameters?)")
         self.t += int(nsteps)
         return self.monitors
+
+    def _wq(self):
+        return None if self.wq is None else _ptr(self.wq)
 
     def collide(self):
         """Collide f(t) -> fpost, u (no time advance)."""
@@ -134,7 +150,7 @@ class O2Sim:
         mon5 = np.zeros(5)
         rc = self.lib.o2_stream(ctypes.byref(self.c), _ptr(self.mask), _ptr(self.coords), _ptr(self.idx),
                                 self.n, _ptr(fpost), _ptr(u), _ptr(self.f), int(t), _ptr(mon5),
-                                self.nthreads)
+                                self.nthreads, self._wq())
         if rc != 0:
             raise RuntimeError("o2_stream failed")
         self.t = int(t) + 1

@@ -22,6 +22,16 @@
  * q = 1/2); moving-wall bounce-back at inlet ghosts with the Womersley
  * velocity at the link midpoint; anti-bounce-back at outlet ghosts with the
  * node's own velocity.
+ *
+ * Curved walls (Sec. 2.1.4, Eq. (9)-(10), the linear interpolation of Bouzidi
+ * et al. that the paper cites): when a wall distance q (fraction of the link
+ * from the node to the wall) is given for the link of node x in direction a
+ * (x + c_a solid), the population returning to x in direction abar is
+ *   q <  1/2: 2q f*_a(x) + (1 - 2q) f*_a(x - c_a)   (x - c_a must be fluid,
+ *             otherwise the link keeps halfway bounce-back),
+ *   q >= 1/2: f*_a(x) / (2q) + (2q - 1) / (2q) f*_abar(x),
+ * both equal to halfway bounce-back at q = 1/2.  The wall force of such a link
+ * is (f*_a(x) + f_abar(x, t + 1)) c_a (momentum exchange).
  */
 #include <complex.h>
 #include <math.h>
@@ -172,7 +182,7 @@ int o2_collide(const o2_case* c, int64_t n, const double* f, double* fpost, doub
  * mon_out[5]: wall force (3), inlet flux, outlet flux. */
 int o2_stream(const o2_case* c, const uint8_t* mask, const int32_t* coords, const int32_t* idx,
               int64_t n, const double* fpost, const double* u, double* fnew, int64_t t,
-              double* mon_out, int nthreads) {
+              double* mon_out, int nthreads, const double* wq) {
     init_tables();
     const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int dims[3] = {nx, ny, nz};
@@ -223,8 +233,27 @@ int o2_stream(const o2_case* c, const uint8_t* mask, const int32_t* coords, cons
                     fnew[27 * i + b] = v;
                     pm[4] += v - src;
                 } else {
-                    fnew[27 * i + b] = src;
-                    for (int d = 0; d < 3; ++d) pm[d] += 2.0 * src * CXYZ[a][d];
+                    double v = src;
+                    const double q = wq ? wq[27 * i + a] : 0.5;
+                    if (q >= 0.5) {
+                        v = src / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fpost[27 * i + b];
+                    } else {
+                        /* the node behind x along -c_a */
+                        int r[3], ok = 1;
+                        for (int d = 0; d < 3; ++d) {
+                            r[d] = p[d] - CXYZ[a][d];
+                            if (per[d]) r[d] = (r[d] + dims[d]) % dims[d];
+                            else if (r[d] < 0 || r[d] >= dims[d]) ok = 0;
+                        }
+                        int64_t j = -1;
+                        if (ok) {
+                            size_t cr = ((size_t)r[2] * ny + r[1]) * nx + r[0];
+                            if (mask[cr] == 1) j = idx[cr];
+                        }
+                        if (j >= 0) v = 2.0 * q * src + (1.0 - 2.0 * q) * fpost[27 * j + a];
+                    }
+                    fnew[27 * i + b] = v;
+                    for (int d = 0; d < 3; ++d) pm[d] += (src + v) * CXYZ[a][d];
                 }
             }
         }
@@ -255,13 +284,13 @@ void o2_mass_momentum(int64_t n, const double* f, double* out) {
  * wall force (3), inlet flux, outlet flux, time of the returned state. */
 int o2_run(const o2_case* c, const uint8_t* mask, const int32_t* coords, const int32_t* idx,
            int64_t n, double* f, double* fpost, double* u, int64_t t0, int nsteps,
-           double* mon, int nthreads) {
+           double* mon, int nthreads, const double* wq) {
     int rc = 0;
     double m5[5] = {0, 0, 0, 0, 0};
     for (int s = 0; s < nsteps; ++s) {
         int64_t t = t0 + s;
         o2_collide(c, n, f, fpost, u, t, nthreads);
-        rc |= o2_stream(c, mask, coords, idx, n, fpost, u, f, t, m5, nthreads);
+        rc |= o2_stream(c, mask, coords, idx, n, fpost, u, f, t, m5, nthreads, wq);
     }
     double mm[4];
     o2_mass_momentum(n, f, mm);

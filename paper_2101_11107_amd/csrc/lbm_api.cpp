@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include <algorithm>
@@ -107,6 +108,8 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.link_meta = (const int32_t*)(base + d->off_lmeta);
     a.link_coef = (const double*)(base + d->off_lcoef);
     a.link_add = (double*)(base + d->off_ladd);
+    a.link_wq = (const double*)(base + d->off_lwq);
+    a.link_off2 = (const uint32_t*)(base + d->off_loff2);
     a.tcount = (int64_t*)(base + d->off_tcount);
     a.trig = (double*)(base + d->off_trig);
     a.cos_w = std::cos(d->omega);
@@ -284,8 +287,16 @@ int lbm_inlet_profile(double r, double t, double radius, double nu, double G0, d
     return LBM_OK;
 }
 
-int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
-                      void* hip_stream, lbm_domain** out) {
+}  // extern "C"
+
+namespace {
+
+// Curved-wall distances keyed by (cell * 27 + alpha_in): alpha_in is the
+// incoming direction of the link, whose source x - c_alpha_in is the wall.
+using WallQ = std::unordered_map<int64_t, double>;
+
+int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                  void* hip_stream, const WallQ* wq, lbm_domain** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!mask) return fail(LBM_EINVAL, "mask is NULL");
@@ -392,6 +403,7 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                         sz[a] = q[2];
                         if (kind[a] == LBM_INLET || kind[a] == LBM_OUTLET) special = true;
                         if (xwrap && kind[a] == LBM_FLUID) special = true;
+                        if (wq && kind[a] == LBM_SOLID && wq->count(d->cell(x, y, z) * 27 + a)) special = true;
                     }
                     if (d->index_of(x, y, z) != i) return fail(LBM_EINVAL, "internal: index mismatch");
                     if (!special) {
@@ -412,7 +424,8 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                                 sp.off[a] = (uint32_t)i;
                                 d->spec_plane.push_back(26 - a);
                                 if (kind[a] == LBM_SOLID) {
-                                    sp.wallmask |= 1u << a;
+                                    if (wq && wq->count(d->cell(x, y, z) * 27 + a)) sp.qmask |= 1u << a;
+                                    else sp.wallmask |= 1u << a;
                                 } else {
                                     const int32_t type = kind[a] == LBM_INLET ? lbm::LINK_INLET : lbm::LINK_OUTLET;
                                     if (type == lbm::LINK_INLET) d->has_inlet_links = true;
@@ -422,8 +435,55 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
                                     d->link_xyz.push_back(y);
                                     d->link_xyz.push_back(z);
                                     for (int q = 0; q < lbm::LINK_COEFS; ++q) d->link_coef.push_back(0.0);
+                                    d->link_wq.push_back(0.0);
+                                    d->link_wq.push_back(0.0);
+                                    d->link_off2.push_back(0u);
+                                    d->link_off2_plane.push_back(0);
                                 }
                             }
+                        }
+                        // curved-wall links (Eq. (9)-(10), linear interpolation), with
+                        // abar = 26 - a the direction towards the wall:
+                        //   q <  1/2: 2q f*_abar(x) + (1 - 2q) f*_abar(x + c_a)
+                        //   q >= 1/2: f*_abar(x) / 2q + (2q - 1) / 2q f*_a(x)
+                        // where x + c_a (the node behind x) must be fluid, else the
+                        // link keeps halfway bounce-back (weights 1, 0).
+                        for (int a = 0; a < 27; ++a) {
+                            if (!((sp.qmask >> a) & 1u)) continue;
+                            const double q = wq->at(d->cell(x, y, z) * 27 + a);
+                            double w0 = 1.0, w1 = 0.0;
+                            int64_t node2 = i;
+                            int plane2 = 26 - a;
+                            if (q >= 0.5) {
+                                w0 = 1.0 / (2.0 * q);
+                                w1 = (2.0 * q - 1.0) / (2.0 * q);
+                                plane2 = a;
+                            } else {
+                                const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+                                int b[3] = {x + c[0], y + c[1], z + c[2]};
+                                bool in = true;
+                                for (int ax = 0; ax < 3; ++ax) {
+                                    if (b[ax] < 0 || b[ax] >= dims[ax]) {
+                                        if (per[ax]) b[ax] = (b[ax] + dims[ax]) % dims[ax];
+                                        else in = false;
+                                    }
+                                }
+                                if (in && mask[d->cell(b[0], b[1], b[2])] == LBM_FLUID) {
+                                    w0 = 2.0 * q;
+                                    w1 = 1.0 - 2.0 * q;
+                                    node2 = d->index_of(b[0], b[1], b[2]);
+                                }
+                            }
+                            d->link_meta.push_back(lbm::LINK_WALL_Q | (a << 8));
+                            d->link_xyz.push_back(x);
+                            d->link_xyz.push_back(y);
+                            d->link_xyz.push_back(z);
+                            for (int k = 0; k < lbm::LINK_COEFS; ++k) d->link_coef.push_back(0.0);
+                            d->link_wq.push_back(w0);
+                            d->link_wq.push_back(w1);
+                            d->link_off2.push_back((uint32_t)node2);
+                            d->link_off2_plane.push_back(plane2);
+                            ++d->ncurved;
                         }
                         d->spec.push_back(sp);
                         d->node_words[i] = lbm::SPECIAL_BIT | (uint32_t)sidx;
@@ -448,6 +508,10 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
             }
         d->spec_plane.clear();
         d->spec_plane.shrink_to_fit();
+        for (size_t k = 0; k < d->link_off2.size(); ++k)
+            d->link_off2[k] = (uint32_t)(((uint64_t)d->link_off2_plane[k] * (uint64_t)npad + d->link_off2[k]) * sb);
+        d->link_off2_plane.clear();
+        d->link_off2_plane.shrink_to_fit();
         d->off_popA = take(d->pop_bytes);
         d->off_popB = take(d->pop_bytes);
         d->off_node = take((size_t)npad * 4);
@@ -457,6 +521,8 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
         d->off_lmeta = take(nl * sizeof(int32_t));
         d->off_lcoef = take(nl * lbm::LINK_COEFS * sizeof(double));
         d->off_ladd = take(nl * sizeof(double));
+        d->off_lwq = take(nl * 2 * sizeof(double));
+        d->off_loff2 = take(nl * sizeof(uint32_t));
         d->off_tcount = take(2 * sizeof(int64_t));
         d->off_trig = take(4 * sizeof(double));
         // monitor partials: one per work-group, for work-groups down to 64 nodes
@@ -470,6 +536,87 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
     }
     *out = d;
     return LBM_OK;
+}
+
+// Cell beyond (x, y, z) along c_alpha with periodic wrap, or -1 outside a
+// non-periodic box.
+int64_t neighbour_cell(int x, int y, int z, int alpha, int nx, int ny, int nz, unsigned periodic_bits) {
+    int p[3] = {x + alpha % 3 - 1, y + (alpha / 3) % 3 - 1, z + alpha / 9 - 1};
+    const int dims[3] = {nx, ny, nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (p[ax] >= 0 && p[ax] < dims[ax]) continue;
+        if (!((periodic_bits >> ax) & 1u)) return -1;
+        p[ax] = (p[ax] + dims[ax]) % dims[ax];
+    }
+    return ((int64_t)p[2] * ny + p[1]) * nx + p[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                      void* hip_stream, lbm_domain** out) {
+    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, nullptr, out);
+}
+
+int lbm_wall_links(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int32_t* links,
+                   int64_t* count) {
+    if (!mask || !count) return fail(LBM_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > lbm::MAX_DIM || ny > lbm::MAX_DIM || nz > lbm::MAX_DIM)
+        return fail(LBM_EINVAL, "dimensions must be in [1, 1023]");
+    if (periodic_bits > 7) return fail(LBM_EINVAL, "periodic_bits must be a combination of LBM_PERIODIC_*");
+    int64_t k = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (mask[((int64_t)z * ny + y) * nx + x] != LBM_FLUID) continue;
+                for (int a = 0; a < 27; ++a) {
+                    if (a == 13) continue;
+                    const int64_t nb = neighbour_cell(x, y, z, a, nx, ny, nz, periodic_bits);
+                    if (nb >= 0 && mask[nb] != LBM_SOLID) continue;
+                    if (links) {
+                        links[4 * k] = x;
+                        links[4 * k + 1] = y;
+                        links[4 * k + 2] = z;
+                        links[4 * k + 3] = a;
+                    }
+                    ++k;
+                }
+            }
+    *count = k;
+    return LBM_OK;
+}
+
+int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                             const int32_t* links, const double* q, int64_t nwall, void* hip_stream,
+                             lbm_domain** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mask || nwall < 0 || (nwall > 0 && (!links || !q))) return fail(LBM_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > lbm::MAX_DIM || ny > lbm::MAX_DIM || nz > lbm::MAX_DIM)
+        return fail(LBM_EINVAL, "dimensions must be in [1, 1023]");
+    if (periodic_bits > 7) return fail(LBM_EINVAL, "periodic_bits must be a combination of LBM_PERIODIC_*");
+    WallQ wq;
+    try {
+        wq.reserve((size_t)nwall);
+        for (int64_t k = 0; k < nwall; ++k) {
+            const int x = links[4 * k], y = links[4 * k + 1], z = links[4 * k + 2], a = links[4 * k + 3];
+            if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz || a < 0 || a > 26 || a == 13)
+                return fail(LBM_EINVAL, "wall link out of range");
+            const int64_t c = ((int64_t)z * ny + y) * nx + x;
+            if (mask[c] != LBM_FLUID) return fail(LBM_EINVAL, "wall link from a cell that is not fluid");
+            const int64_t nb = neighbour_cell(x, y, z, a, nx, ny, nz, periodic_bits);
+            if (nb >= 0 && mask[nb] != LBM_SOLID) return fail(LBM_EINVAL, "wall link does not end in a solid cell");
+            if (!std::isfinite(q[k]) || !(q[k] > 0.0) || !(q[k] <= 1.0))
+                return fail(LBM_EINVAL, "wall distance q must be in (0, 1]");
+            // keyed by the incoming direction 26 - a of the bounced population
+            if (!wq.emplace(c * 27 + (26 - a), q[k]).second) return fail(LBM_EINVAL, "duplicate wall link");
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "host allocation failed");
+    }
+    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, &wq, out);
 }
 
 int lbm_device_bytes(const lbm_domain* d, size_t* bytes) {
@@ -493,9 +640,14 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     if (!d->spec.empty())
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_spec, d->spec.data(), d->spec.size() * sizeof(SpecialNode),
                                hipMemcpyHostToDevice, st), "upload of special nodes");
-    if (d->nlinks())
+    if (d->nlinks()) {
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_lmeta, d->link_meta.data(), d->nlinks() * sizeof(int32_t),
                                hipMemcpyHostToDevice, st), "upload of link table");
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_lwq, d->link_wq.data(), d->link_wq.size() * sizeof(double),
+                               hipMemcpyHostToDevice, st), "upload of curved-wall weights");
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_loff2, d->link_off2.data(), d->link_off2.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, st), "upload of curved-wall offsets");
+    }
     d->links_dirty = true;
     d->initialized = false;
     d->monitored = false;

@@ -25,8 +25,17 @@ __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int ste
         a.tin ^= 1;
     }
     const int lb = packed & ITEM_BLOCK_MASK;
-    if (a.periodic & 6) step_block<S, MON, ONE, true, NT, BS>(a, lb);
-    else step_block<S, MON, ONE, false, NT, BS>(a, lb);
+    // ONE: every domain of the batch has free rates of one.  Otherwise each
+    // item takes its own domain's collision form, as the domain's own step
+    // would (the two forms round differently).
+    const bool one = ONE || (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0);
+    if (one) {
+        if (a.periodic & 6) step_block<S, MON, true, true, NT, BS>(a, lb);
+        else step_block<S, MON, true, false, NT, BS>(a, lb);
+    } else {
+        if (a.periodic & 6) step_block<S, MON, false, true, NT, BS>(a, lb);
+        else step_block<S, MON, false, false, NT, BS>(a, lb);
+    }
 }
 
 template <class S, bool MON, bool ONE, bool NT, int BS>

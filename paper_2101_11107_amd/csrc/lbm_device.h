@@ -334,10 +334,11 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
     }
 }
 
-// Node with open-boundary or periodic-x links: explicit byte offsets, then the
-// open-boundary corrections with the additive terms prepared by the previous
-// step (or the initial state): inlet f_a = f*_abar + add, outlet
-// f_a = -f*_abar + add (evaluated in FP64, rounded once).
+// Node with open-boundary, periodic-x or curved-wall links: explicit byte
+// offsets, then the open-boundary corrections with the additive terms prepared
+// by the previous step (or the initial state): inlet f_a = f*_abar + add,
+// outlet f_a = -f*_abar + add (evaluated in FP64, rounded once); then the
+// curved-wall blends.
 template <class S, bool MON>
 __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a,
                                                const LBM_GLOBAL SpecialNode* __restrict__ sp,
@@ -376,6 +377,36 @@ __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict
                 }
                 ++l;
             }
+        }
+    }
+    const uint32_t qm = sp->qmask;
+    if (qm) {
+        // curved walls (Eq. (9)-(10)): f_a = w0 f*_abar(x) + w1 f2 with the
+        // weights and the second value chosen on the host from the wall
+        // distance; the wall force is (f*_abar(x) + f_a) c_abar per link
+        // (momentum exchange).  Shifted populations blend the same way: the
+        // weights sum to one and w_a = w_abar.
+        // One direction at a time, with a scheduling barrier between them:
+        // this rare path must not raise the register count of the whole step
+        // (hoisting its loads together would).
+        int l = sp->link0 + __popc(lm);
+        const LBM_GLOBAL double* wq = (const LBM_GLOBAL double*)a.link_wq;
+        const LBM_GLOBAL uint32_t* off2 = (const LBM_GLOBAL uint32_t*)a.link_off2;
+#pragma unroll
+        for (int al = 0; al < 27; ++al) {
+            if ((qm >> al) & 1u) {
+                const T own = f[al];
+                const T v = (T)wq[2 * l] * own + (T)wq[2 * l + 1] * ldp<S>(fin, off2[l]);
+                f[al] = v;
+                if (MON) {
+                    const double s = (double)own + (double)v + 2.0 * wgt(al);
+                    F[0] -= s * cxo(al);
+                    F[1] -= s * cyo(al);
+                    F[2] -= s * czo(al);
+                }
+                ++l;
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }

@@ -51,6 +51,10 @@ struct lbm_domain {
     std::vector<int32_t> link_meta;        // [nlinks] type | alpha << 8
     std::vector<double> link_coef;         // [nlinks][LINK_COEFS]
     std::vector<int32_t> link_xyz;         // [nlinks][3] node coordinates of each link
+    std::vector<double> link_wq;           // [nlinks][2] curved-wall weights (0 for other links)
+    std::vector<uint32_t> link_off2;       // [nlinks] second value of a curved-wall link (element, then byte)
+    std::vector<int32_t> link_off2_plane;  // [nlinks] its plane (until the layout is fixed)
+    int64_t ncurved = 0;                   // curved-wall links
     std::vector<int32_t> coords;           // [n][3]
     bool has_inlet_links = false;
     size_t nlinks() const { return link_meta.size(); }
@@ -67,7 +71,8 @@ struct lbm_domain {
     char* dev = nullptr;
     size_t dev_bytes = 0;
     size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
-           off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0;
+           off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0,
+           off_lwq = 0, off_loff2 = 0;
     size_t pop_bytes = 0;
 
     int cur = 0;

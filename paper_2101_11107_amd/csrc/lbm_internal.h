@@ -29,22 +29,25 @@ struct alignas(8) RowEntry {
     int32_t prefix;
 };
 
-// Record of a node with open-boundary or periodic-x links.  off[alpha] is the
-// byte offset (from the population buffer) of the value it pulls: the source
-// node's alpha population for a fluid link, its own abar population for a wall
-// or open link (bounce-back).  Open links then get the boundary correction:
-// inlet f += add, outlet f = -f + add.  Links are numbered from link0 in
-// increasing alpha.
+// Record of a node with open-boundary, periodic-x or curved-wall links.
+// off[alpha] is the byte offset (from the population buffer) of the value it
+// pulls: the source node's alpha population for a fluid link, its own abar
+// population for a wall or open link (bounce-back).  Open links then get the
+// boundary correction: inlet f += add, outlet f = -f + add.  Curved-wall links
+// (Eq. (9)-(10)) blend that value with a second one: f = w0 f + w1 f2.  The
+// node's links are numbered from link0: its open links in increasing alpha,
+// then its curved-wall links in increasing alpha.
 struct alignas(16) SpecialNode {
     uint32_t off[27];
     int32_t node;          // fluid-node index
-    int32_t link0;         // first open-boundary link of this node
-    uint32_t wallmask;     // bit alpha: wall link
+    int32_t link0;         // first link of this node
+    uint32_t wallmask;     // bit alpha: halfway bounce-back wall link
     uint32_t linkmask;     // bit alpha: open-boundary link
+    uint32_t qmask;        // bit alpha: curved-wall link
 };
 static_assert(sizeof(SpecialNode) == 128, "special node record is 128 bytes");
 
-enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3 };
+enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3, LINK_WALL_Q = 4 };
 
 // Per open-boundary link: meta = type | alpha << 8; coef = (a0, a1re, a1im,
 // k1, k3, k5): the inlet speed at the link midpoint is
@@ -63,6 +66,8 @@ struct StepArgs {
     const int32_t* link_meta;    // [nlinks]
     const double* link_coef;     // [nlinks][LINK_COEFS]
     double* link_add;            // [nlinks]
+    const double* link_wq;       // [nlinks][2] curved-wall weights (w0, w1)
+    const uint32_t* link_off2;   // [nlinks] byte offset of a curved-wall link's second value
     int64_t* tcount;             // [2] time counters (read slot tin, write slot tin ^ 1)
     double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials

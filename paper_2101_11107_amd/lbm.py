@@ -26,7 +26,8 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
 
 EXPORTED = [
-    "lbm_last_error", "lbm_create_domain", "lbm_device_bytes", "lbm_attach_device",
+    "lbm_last_error", "lbm_create_domain", "lbm_create_domain_curved", "lbm_wall_links",
+    "lbm_device_bytes", "lbm_attach_device",
     "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_inlet_womersley",
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
     "lbm_average", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
@@ -67,6 +68,10 @@ def load():
         "lbm_last_error": ([], ctypes.c_char_p),
         "lbm_create_domain": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int, _P,
                                ctypes.POINTER(_P)], ctypes.c_int),
+        "lbm_create_domain_curved": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int,
+                                      _P, _P, ctypes.c_int64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "lbm_wall_links": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _P,
+                            ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
         "lbm_fluid_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -149,6 +154,36 @@ def lbm_create_domain(mask: np.ndarray, periodic_bits: int, storage: int, hip_st
     out = _P()
     _check(load().lbm_create_domain(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), int(storage),
                                     _P(hip_stream), ctypes.byref(out)))
+    return out
+
+
+def lbm_create_domain_curved(mask: np.ndarray, periodic_bits: int, storage: int, links: np.ndarray,
+                             q: np.ndarray, hip_stream: int):
+    """Domain with interpolated bounce-back on the listed wall links:
+    links int32 [m, 4] = (x, y, z, alpha towards the wall), q float64 [m]."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = m.shape
+    lk = np.ascontiguousarray(links, np.int32).reshape(-1, 4)
+    qq = np.ascontiguousarray(q, np.float64).reshape(-1)
+    if len(lk) != len(qq):
+        raise ValueError("links and q differ in length")
+    out = _P()
+    _check(load().lbm_create_domain_curved(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), int(storage),
+                                           lk.ctypes.data_as(_P), qq.ctypes.data_as(_P), len(qq),
+                                           _P(hip_stream), ctypes.byref(out)))
+    return out
+
+
+def lbm_wall_links(mask: np.ndarray, periodic_bits: int) -> np.ndarray:
+    """Wall links of a mask: int32 [m, 4] = (x, y, z, alpha towards the wall)."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = m.shape
+    cnt = ctypes.c_int64()
+    _check(load().lbm_wall_links(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), None, ctypes.byref(cnt)))
+    out = np.zeros((cnt.value, 4), np.int32)
+    if cnt.value:
+        _check(load().lbm_wall_links(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits),
+                                     out.ctypes.data_as(_P), ctypes.byref(cnt)))
     return out
 
 
@@ -308,9 +343,11 @@ class Domain:
 
     ``case`` is any object with ``mask``, ``periodic``, ``tau``, ``rates``,
     ``g``, ``rho_out`` and ``inlet`` attributes (see the ``synth`` package).
+    ``wall_q``: optional (links [m, 4], q [m]) for curved walls (interpolated
+    bounce-back on those links, see ``lbm_create_domain_curved``).
     """
 
-    def __init__(self, case, storage="f32", device="cuda:0", stream=None):
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None, wall_q=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required (the library has no CPU path)")
@@ -321,7 +358,11 @@ class Domain:
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.case = case
-        self.handle = lbm_create_domain(case.mask, case.periodic, self.storage, self.stream.cuda_stream)
+        if wall_q is None:
+            self.handle = lbm_create_domain(case.mask, case.periodic, self.storage, self.stream.cuda_stream)
+        else:
+            self.handle = lbm_create_domain_curved(case.mask, case.periodic, self.storage, wall_q[0], wall_q[1],
+                                                   self.stream.cuda_stream)
         self.n = lbm_fluid_count(self.handle)
         nbytes = lbm_device_bytes(self.handle)
         self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

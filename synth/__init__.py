@@ -16,3 +16,4 @@ from .geometry import (  # noqa: F401
     Case, pipe_case, aneurysm_case, batch_cases, fluid_count,
     random_tiny_case, periodic_box_case, channel_case,
 )
+from .walls import wall_links, fluid_predicate, wall_distances, random_wall_distances  # noqa: F401

@@ -14,12 +14,13 @@ def oracle_order(coords, mask):
     return np.argsort(key, kind="stable")
 
 
-def gpu_run(case, storage, steps, device="cuda:0"):
+def gpu_run(case, storage, steps, device="cuda:0", wall_q=None):
     """Run the HIP path; return (domain, shifted post-collision populations [n, 27]
-    as FP64, in the oracle's x-fastest node order)."""
+    as FP64, in the oracle's x-fastest node order).  wall_q: optional
+    (links [m, 4], q [m]) for curved walls."""
     import torch
     from paper_2101_11107_amd import lbm
-    dom = lbm.Domain(case, storage=storage, device=device)
+    dom = lbm.Domain(case, storage=storage, device=device, wall_q=wall_q)
     dom.init()
     if steps:
         dom.step(steps)
@@ -29,10 +30,13 @@ def gpu_run(case, storage, steps, device="cuda:0"):
     return dom, f[perm]
 
 
-def oracle_post(case, steps, nthreads=16):
-    """Oracle tier O2: shifted post-collision populations f*(steps) - w and u(steps)."""
+def oracle_post(case, steps, nthreads=16, wall_q=None):
+    """Oracle tier O2: shifted post-collision populations f*(steps) - w and u(steps).
+    wall_q: optional (links [m, 4], q [m]) for curved walls."""
     from oracle import o2
-    sim = o2.O2Sim(case, nthreads=nthreads)
+    wq = None if wall_q is None else {tuple(int(v) for v in lk): float(q)
+                                      for lk, q in zip(wall_q[0], wall_q[1])}
+    sim = o2.O2Sim(case, nthreads=nthreads, wall_q=wq)
     if steps:
         sim.run(steps)
     rho, u = sim.macroscopic()

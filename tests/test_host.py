@@ -94,3 +94,57 @@ def test_parameter_validation_and_call_order():
         assert e.value.code == lbm.LBM_ESTATE
     finally:
         lbm.lbm_destroy(dom)
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.random_tiny_case(1, nx=11, ny=9, nz=8),
+                                   lambda: synth.random_tiny_case(4, nx=31, ny=6, nz=5),
+                                   lambda: synth.pipe_case(),
+                                   lambda: synth.aneurysm_case(64, 2)])
+def test_wall_links_match_an_independent_enumeration(maker):
+    """lbm_wall_links lists the same (cell, direction) pairs, in the same
+    order, as the seeded-input module's own enumeration from the mask."""
+    lbm = _lbm()
+    case = maker()
+    got = lbm.lbm_wall_links(case.mask, case.periodic)
+    ref = synth.wall_links(case.mask, case.periodic)
+    assert got.shape == ref.shape and len(got) > 0
+    assert np.array_equal(got, ref)
+
+
+def test_curved_domain_validation_and_size():
+    """Curved-wall links are checked one by one (EINVAL); a valid list turns
+    the nodes that carry one into explicit-offset nodes, so the device
+    footprint grows."""
+    lbm = _lbm()
+    case = synth.random_tiny_case(2, nx=11, ny=9, nz=8)
+    links = synth.wall_links(case.mask, case.periodic)
+    q = synth.random_wall_distances(links, 0)
+    plain = lbm.lbm_create_domain(case.mask, case.periodic, lbm.LBM_F64, 0)
+    curved = lbm.lbm_create_domain_curved(case.mask, case.periodic, lbm.LBM_F64, links, q, 0)
+    assert lbm.lbm_device_bytes(curved) > lbm.lbm_device_bytes(plain)
+    assert lbm.lbm_fluid_count(curved) == lbm.lbm_fluid_count(plain)
+    lbm.lbm_destroy(plain)
+    lbm.lbm_destroy(curved)
+    fluid = np.argwhere(case.mask == synth.FLUID)[0]            # (z, y, x)
+    notwall = None
+    for a in range(27):
+        cand = np.array([fluid[2], fluid[1], fluid[0], a], np.int32)
+        if a != 13 and not any(np.array_equal(cand, l) for l in links):
+            notwall = cand
+            break
+    solid = np.argwhere(case.mask == synth.SOLID)[0]
+    bad_cases = [
+        (links[:1], np.array([0.0])),                                   # q = 0
+        (links[:1], np.array([1.5])),                                   # q > 1
+        (links[:1], np.array([np.nan])),
+        (np.concatenate([links[:1], links[:1]]), np.array([0.3, 0.4])),  # duplicate
+        (np.array([[solid[2], solid[1], solid[0], links[0, 3]]], np.int32), np.array([0.3])),
+        (np.array([[links[0, 0], links[0, 1], links[0, 2], 13]], np.int32), np.array([0.3])),
+        (np.array([[99, 0, 0, 0]], np.int32), np.array([0.3])),
+    ]
+    if notwall is not None:
+        bad_cases.append((notwall[None, :], np.array([0.3])))
+    for lk, qq in bad_cases:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_create_domain_curved(case.mask, case.periodic, lbm.LBM_F64, lk, qq, 0)
+        assert e.value.code == lbm.LBM_EINVAL

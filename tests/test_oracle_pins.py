@@ -417,3 +417,55 @@ def test_oracle_catches_planted_mistakes(o2lib, monkeypatch):
     bad = o1.run(case, 5).f
     monkeypatch.setattr(o1, "relaxation_rates", orig_rates)
     assert np.max(np.abs(bad - ref)) > 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Curved walls (Sec. 2.1.4, Eq. (9)-(10)): linear interpolated bounce-back
+# ---------------------------------------------------------------------------
+
+def _wall_q_map(links, q):
+    return {tuple(int(v) for v in lk): float(qq) for lk, qq in zip(links, q)}
+
+
+@pytest.mark.parametrize("seed", [0, 1, 3])
+def test_P16_curved_walls_at_half_equal_halfway_bounce_back(o2lib, seed):
+    """q = 1/2 on every wall link is halfway bounce-back (both branches of
+    Eq. (9) reduce to it): identical populations and monitors, bit for bit."""
+    case = synth.random_tiny_case(seed)
+    links = synth.wall_links(case.mask, case.periodic)
+    assert len(links) > 0
+    a = o2lib.O2Sim(case, nthreads=2)
+    b = o2lib.O2Sim(case, nthreads=2, wall_q=_wall_q_map(links, np.full(len(links), 0.5)))
+    ma, mb = a.run(15).copy(), b.run(15).copy()
+    assert np.array_equal(a.f, b.f)
+    assert np.array_equal(ma, mb)
+
+
+def _pipe_error_curved(o2lib, R, curved):
+    """L2 error of the axial velocity against the Poiseuille start-up series
+    after 20 R^2 steps (diffusive scaling), pipe axis off the lattice."""
+    n = int(2 * R + 4)
+    c = synth.pipe_case(nx=4, ny=n, nz=n, radius=R, center=((n - 1) / 2 + 0.3, (n - 1) / 2 - 0.2))
+    wq = None
+    if curved:
+        links = synth.wall_links(c.mask, c.periodic)
+        wq = _wall_q_map(links, synth.wall_distances(c, links))
+    steps = int(20 * R * R)
+    sim = o2lib.O2Sim(c, nthreads=8, wall_q=wq)
+    sim.run(steps)
+    _, u = sim.macroscopic()
+    cy, cz = c.meta["center"]
+    y, z = sim.coords[:, 1] - cy, sim.coords[:, 2] - cz
+    ua = _poiseuille_startup(np.sqrt(y * y + z * z), steps, R, c.nu, 1e-6)
+    return math.sqrt(((u[:, 0] - ua) ** 2).sum() / (ua ** 2).sum())
+
+
+def test_P17_curved_walls_converge_at_second_order(o2lib):
+    """Pipe Poiseuille with the exact wall distance of the circular wall: the
+    error falls by about 4 per halving of the grid spacing (second order),
+    against about 2 for halfway bounce-back on the staircase (first order)."""
+    e = {R: _pipe_error_curved(o2lib, R, True) for R in (5, 10, 20)}
+    h = {R: _pipe_error_curved(o2lib, R, False) for R in (5, 10, 20)}
+    assert e[5] / e[10] > 3.5 and e[10] / e[20] > 3.5
+    assert h[5] / h[10] < 2.8 and h[10] / h[20] < 2.8
+    assert e[20] < 1e-3 < h[20]
