@@ -67,8 +67,8 @@ def read_traffic(storage, workload):
         return None
 
 
-def run_form(torch, lbm, case, storage, warmup, steps, want_u=False):
-    dom = lbm.Domain(case, storage=storage, device="cuda:0")
+def run_form(torch, lbm, case, storage, warmup, steps, want_u=False, wall_q=None):
+    dom = lbm.Domain(case, storage=storage, device="cuda:0", wall_q=wall_q)
     dom.init()
     dom.step(warmup)
     dom.stream.synchronize()
@@ -90,6 +90,52 @@ def run_form(torch, lbm, case, storage, warmup, steps, want_u=False):
     dom.close()
     del dom
     torch.cuda.empty_cache()
+    return out
+
+
+def curved_bench(torch, lbm, case, storage, warmup, steps, plain):
+    """Curved walls (interpolated bounce-back with the exact wall distance on
+    every wall link of the geometry): the step rate against the plain halfway
+    form of the same run, and the pipe Poiseuille error of both wall rules
+    against the start-up series at R = 5, 10, 20 (FP64, 20 R^2 steps)."""
+    import numpy as np
+    import scipy.special
+    import synth
+    links = synth.wall_links(case.mask, case.periodic)
+    q = synth.wall_distances(case, links)
+    r = run_form(torch, lbm, case, storage, warmup, steps, want_u=True, wall_q=(links, q))
+    rf = roofline(r["n"], r["ms_per_step"], storage, None)
+    out = {"workload": case.name.split("_")[0] + "_curved_walls", "storage": storage, "wall_links": int(len(links)),
+           "mlups": round(r["mlups"], 1), "roofline_frac": rf["frac"],
+           "rate_vs_halfway": round(r["mlups"] / plain["mlups"], 3)}
+    if "u" in plain:
+        out["u_rel_l2_vs_halfway"] = rel_l2(r["u"], plain["u"])
+    lam = scipy.special.jn_zeros(0, 60)
+    errs = {"halfway": [], "curved": []}
+    for R in (5, 10, 20):
+        n = int(2 * R + 4)
+        pc = synth.pipe_case(nx=4, ny=n, nz=n, radius=R, center=((n - 1) / 2 + 0.3, (n - 1) / 2 - 0.2))
+        pl = synth.wall_links(pc.mask, pc.periodic)
+        pq = synth.wall_distances(pc, pl)
+        nsteps = int(20 * R * R)
+        cy, cz = pc.meta["center"]
+        for kind, wq in (("halfway", None), ("curved", (pl, pq))):
+            dom = lbm.Domain(pc, storage="f64", device="cuda:0", wall_q=wq)
+            dom.init()
+            dom.step(nsteps)
+            _, u = dom.moments()
+            u = u.cpu().numpy()
+            xyz = dom.coords()
+            dom.close()
+            rr = np.sqrt((xyz[:, 1] - cy) ** 2 + (xyz[:, 2] - cz) ** 2)
+            nu, g = pc.nu, pc.g[0]
+            ua = g * (R * R - rr * rr) / (4 * nu)
+            for lv in lam:
+                ua = ua - 2 * g * R * R / nu * scipy.special.j0(lv * rr / R) / (lv ** 3 * scipy.special.j1(lv)) \
+                    * np.exp(-lv * lv * nu * nsteps / (R * R))
+            errs[kind].append(float(np.sqrt(((u[0] - ua) ** 2).sum() / (ua ** 2).sum())))
+    out["pipe_l2_error_R5_10_20"] = {k: [round(e, 7) for e in v] for k, v in errs.items()}
+    out["pipe_order"] = {k: round(float(np.log2(v[1] / v[2])), 2) for k, v in errs.items()}
     return out
 
 
@@ -296,6 +342,8 @@ def main():
                     row["mass_drift_vs_f64"] = abs(r["monitors"][0] - ref["monitors"][0]) / ref["monitors"][0]
                 also.append(row)
             del ref
+        also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, main_run))
+        note(f"curved walls: {also[-1]['mlups']:.1f} MLUPS, pipe order {also[-1]['pipe_order']}")
         also.append(batch_bench(torch, lbm, 480))
         note(f"batch: {also[-1]['batched_mlups']:.1f} MLUPS batched")
         if not args.no_corrector:
