@@ -181,6 +181,36 @@ def collide(f: np.ndarray, tau: float, rates, g) -> tuple:
     return f_post, rho, j, u
 
 
+# --- SRT comparator (Sec. 2.1.1-2.1.2) ------------------------------------------
+
+def equilibrium_second_order(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """The classical EDF: Eq. (3) truncated after the second-order term,
+    w [rho + rho c.u / cs^2 + rho ((c.u)^2 - cs^2 u.u) / (2 cs^4)]."""
+    cu = u @ C.T.astype(np.float64)                      # [N, 27]
+    uu = (u * u).sum(axis=1)[:, None]
+    return W[None, :] * rho[:, None] * (1.0 + cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2))
+
+
+def guo_force(rho: np.ndarray, u: np.ndarray, g) -> np.ndarray:
+    """Force populations of Guo et al. for a force density rho g:
+    w [(c - u) / cs^2 + (c.u) c / cs^4] . rho g."""
+    gv = np.asarray(g, np.float64)
+    Cf = C.astype(np.float64)
+    cu = u @ Cf.T
+    cg = Cf @ gv                                         # [27]
+    ug = u @ gv                                          # [N]
+    return W[None, :] * rho[:, None] * ((cg[None, :] - ug[:, None]) / CS2 + cu * cg[None, :] / (CS2 * CS2))
+
+
+def collide_srt2(f: np.ndarray, tau: float, g) -> tuple:
+    """Single-relaxation-time collision (Eq. (2)) towards the second-order EDF,
+    with Guo's force term: f* = f + (f_eq2 - f) / tau + (1 - 1/(2 tau)) F.
+    u = (j + rho g / 2) / rho as for CHM-MRT, so a step adds rho g of momentum."""
+    rho, j, u = moments(f, g)
+    f_post = f + (equilibrium_second_order(rho, u) - f) / tau + (1.0 - 0.5 / tau) * guo_force(rho, u, g)
+    return f_post, rho, j, u
+
+
 # --- Inlet profile --------------------------------------------------------------
 
 def womersley_speed(r: np.ndarray, t: float, radius: float, nu: float,
@@ -317,7 +347,10 @@ def step(state: O1State) -> None:
     """Advance the dense state by one time step (collide, then push-stream)."""
     fl = state.fluid
     f_nodes = state.f[fl[:, 0], fl[:, 1], fl[:, 2]]
-    f_post, rho, j, u = collide(f_nodes, state.case.tau, state.rates(), state.g_at(state.t))
+    if getattr(state.case, "collision", "chm_mrt") == "srt2":
+        f_post, rho, j, u = collide_srt2(f_nodes, state.case.tau, state.g_at(state.t))
+    else:
+        f_post, rho, j, u = collide(f_nodes, state.case.tau, state.rates(), state.g_at(state.t))
     state.u_last[fl[:, 0], fl[:, 1], fl[:, 2]] = u
     new, fwall, q_in, q_out = stream(state, f_post, u)
     state.f = new

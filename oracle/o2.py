@@ -35,7 +35,7 @@ class _Case(ctypes.Structure):
                 ("rho_out", ctypes.c_double), ("has_inlet", ctypes.c_int),
                 ("axis", ctypes.c_double * 3), ("center", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("G0", ctypes.c_double), ("G1", ctypes.c_double),
-                ("omega", ctypes.c_double), ("nu", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("collision", ctypes.c_int)]
 
 
 _lib = None
@@ -111,6 +111,7 @@ class O2Sim:
             c.radius, c.G0, c.G1, c.omega = (float(case.inlet.radius), float(case.inlet.G0),
                                              float(case.inlet.G1), float(case.inlet.omega))
         c.nu = (case.tau - 0.5) / 3.0
+        c.collision = 1 if getattr(case, "collision", "chm_mrt") == "srt2" else 0
         self.c = c
         self.wq = None
         if wall_q is not None:

@@ -50,6 +50,7 @@ typedef struct {
     double rho_out;
     int has_inlet;
     double axis[3], center[3], radius, G0, G1, omega, nu;
+    int collision;              /* 0 CHM-MRT, 1 SRT with the second-order EDF */
 } o2_case;
 
 static int CXYZ[27][3];
@@ -160,6 +161,35 @@ static void collide_node(const o2_case* c, const double* f, double* fp, double* 
     for (int d = 0; d < 3; ++d) uo[d] = u[d];
 }
 
+/* SRT comparator (Sec. 2.1.1-2.1.2): BGK relaxation (Eq. (2)) towards the
+ * equilibrium of Eq. (3) cut after its second-order term,
+ *   feq2_a = w_a rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
+ * plus Guo's force populations (1 - 1/(2 tau)) w_a rho [3 (c - u).g + 9 (c.u)(c.g)];
+ * u = (j + rho g / 2) / rho as for CHM-MRT. */
+static void collide_node_srt2(const o2_case* c, const double* f, double* fp, double* uo, const double g[3]) {
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int a = 0; a < 27; ++a) {
+        rho += f[a];
+        for (int d = 0; d < 3; ++d) j[d] += CXYZ[a][d] * f[a];
+    }
+    double u[3];
+    for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * rho * g[d]) / rho;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+    const double om = 1.0 / c->tau;
+    for (int a = 0; a < 27; ++a) {
+        double cu = 0, cg = 0;
+        for (int d = 0; d < 3; ++d) {
+            cu += CXYZ[a][d] * u[d];
+            cg += CXYZ[a][d] * g[d];
+        }
+        const double feq = WGT[a] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double F = WGT[a] * rho * (3.0 * (cg - ug) + 9.0 * cu * cg);
+        fp[a] = f[a] - om * (f[a] - feq) + (1.0 - 0.5 * om) * F;
+    }
+    for (int d = 0; d < 3; ++d) uo[d] = u[d];
+}
+
 static void g_at(const o2_case* c, int64_t t, double g[3]) {
     double cs = cos(c->omega_g * (double)t);
     for (int d = 0; d < 3; ++d) g[d] = c->g0[d] + c->g1[d] * cs;
@@ -173,7 +203,10 @@ int o2_collide(const o2_case* c, int64_t n, const double* f, double* fpost, doub
     g_at(c, t, g);
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) collide_node(c, f + 27 * i, fpost + 27 * i, u + 3 * i, g);
+    for (int64_t i = 0; i < n; ++i) {
+        if (c->collision == 1) collide_node_srt2(c, f + 27 * i, fpost + 27 * i, u + 3 * i, g);
+        else collide_node(c, f + 27 * i, fpost + 27 * i, u + 3 * i, g);
+    }
     return 0;
 }
 

@@ -67,6 +67,7 @@ class Case:
     period: int = 0
     seed: int = 0
     meta: dict = dataclasses.field(default_factory=dict)
+    collision: str = "chm_mrt"        # or "srt2": single relaxation time, second-order EDF
 
     @property
     def shape(self):

@@ -5,6 +5,7 @@ itself: closed forms, invariants, special cases reducing to textbook results
 and brute force between the two independent oracle tiers.
 """
 
+import dataclasses
 import math
 import os
 
@@ -469,3 +470,82 @@ def test_P17_curved_walls_converge_at_second_order(o2lib):
     assert e[5] / e[10] > 3.5 and e[10] / e[20] > 3.5
     assert h[5] / h[10] < 2.8 and h[10] / h[20] < 2.8
     assert e[20] < 1e-3 < h[20]
+
+
+# ---------------------------------------------------------------------------
+# SRT comparator (Sec. 2.1.1-2.1.2): BGK with the second-order EDF
+# ---------------------------------------------------------------------------
+
+def test_P18_second_order_edf_and_force_moments():
+    """The truncated EDF keeps exactly the moments it is built to match --
+    rho, rho u and rho (u u + cs^2 I) -- and Guo's force populations carry no
+    mass, momentum rho g and second moment rho (u g + g u)."""
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.9, 1.1, 50)
+    u = rng.uniform(-0.08, 0.08, (50, 3))
+    g = np.array([2e-4, -1e-4, 3e-4])
+    feq = o1.equilibrium_second_order(rho, u)
+    Cf = o1.C.astype(np.float64)
+    assert np.allclose(feq.sum(1), rho, rtol=0, atol=1e-15)
+    assert np.allclose(feq @ Cf, rho[:, None] * u, rtol=0, atol=1e-15)
+    P = np.einsum("na,ai,aj->nij", feq, Cf, Cf)
+    assert np.allclose(P, rho[:, None, None] * (u[:, :, None] * u[:, None, :] + np.eye(3) / 3.0), rtol=0, atol=1e-15)
+    # it differs from the full expansion only at third order in u
+    full = o1.equilibrium_product(rho, u)
+    d1 = np.abs(full - feq).max()
+    d2 = np.abs(o1.equilibrium_product(rho, u / 2) - o1.equilibrium_second_order(rho, u / 2)).max()
+    assert 6.0 < d1 / d2 < 10.0
+    F = o1.guo_force(rho, u, g)
+    assert np.allclose(F.sum(1), 0.0, atol=1e-18)
+    assert np.allclose(F @ Cf, rho[:, None] * g[None, :], rtol=0, atol=1e-18)
+    S = np.einsum("na,ai,aj->nij", F, Cf, Cf)
+    ug = u[:, :, None] * g[None, None, :]
+    assert np.allclose(S, rho[:, None, None] * (ug + ug.transpose(0, 2, 1)), rtol=0, atol=1e-18)
+
+
+def _srt(case):
+    return dataclasses.replace(case, collision="srt2")
+
+
+def test_P19_srt_shear_wave_and_momentum(o2lib):
+    """SRT with the second-order EDF: a shear wave decays at nu = (tau - 1/2)/3
+    (truncation error of order k^2), and a periodic box gains M g per step."""
+    def rate_error(L, tau):
+        case = _srt(synth.periodic_box_case(4, L, 1, tau=tau))
+        sim = o2lib.O2Sim(case, nthreads=4)
+        y = sim.coords[:, 1]
+        shape = np.sin(2 * np.pi * y / L)
+        u0 = np.zeros((sim.n, 3))
+        u0[:, 0] = 1e-3 * shape
+        sim.f[...] = o1.equilibrium_second_order(np.ones(sim.n), u0)
+        amps = []
+        t1, t2 = (L * L) // 10, (3 * L * L) // 10
+        for t in (t1, t2):
+            sim.run(t - sim.t)
+            _, u = sim.macroscopic()
+            amps.append((u[:, 0] * shape).sum() / (shape * shape).sum())
+        rate = -math.log(amps[1] / amps[0]) / (t2 - t1)
+        return rate / (case.nu * (2 * math.pi / L) ** 2) - 1.0
+    for tau in (0.8, 0.6):
+        e32, e64 = rate_error(32, tau), rate_error(64, tau)
+        assert abs(e32) < 5e-3 and abs(e64) < abs(e32) / 3.0
+    case = _srt(synth.periodic_box_case(6, 5, 4, tau=0.9, g=(2e-5, -1e-5, 3e-5)))
+    sim = o2lib.O2Sim(case, nthreads=2)
+    for t in (7, 50):
+        mon = sim.run(t - sim.t)
+        expect = mon[0] * np.asarray(case.g) * t
+        assert np.max(np.abs(mon[1:4] - expect)) < 1e-12 * np.max(np.abs(expect)) + 1e-16
+        assert abs(mon[0] - sim.n) < 1e-11
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_P20_srt_dense_and_fast_oracles_agree(o2lib, seed):
+    """Tiny random masks (walls, periodic axes, inlet and outlet ghosts, force):
+    the dense SRT collision of O1 equals the one of O2."""
+    case = _srt(synth.random_tiny_case(seed))
+    st = o1.run(case, 20)
+    sim = o2lib.O2Sim(case, nthreads=2)
+    sim.run(20)
+    fl = st.fluid
+    assert np.max(np.abs(st.f[fl[:, 0], fl[:, 1], fl[:, 2]] - sim.f)) < 1e-13
+    assert np.max(np.abs(st.monitors - sim.monitors)) < 1e-12
