@@ -143,6 +143,19 @@ int lbm_fluid_coords(const lbm_domain* dom, int32_t* xyz);
  * EINVAL unless tau > 1/2, every s in (0, 2), all values finite. */
 int lbm_set_params(lbm_domain* dom, const lbm_params* p);
 
+/* Collision operator of a domain.  LBM_COLLISION_CHM_MRT (the default) is the
+ * central Hermite MRT collision with the full equilibrium (Eq. (6)-(8)).
+ * LBM_COLLISION_SRT2 is the classical comparator of Sec. 2.1.1-2.1.2: BGK
+ * relaxation (Eq. (2)) with rate 1/tau towards the equilibrium of Eq. (3) cut
+ * after its second-order term, w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
+ * with Guo's force populations (1 - 1/(2 tau)) w rho [3 (c - u).g
+ * + 9 (c.u)(c.g)] and the same u = (j + rho g / 2) / rho; the free rates of
+ * lbm_params are not used.  lbm_init_equilibrium then starts from that
+ * operator's own equilibrium.  May be called at any time; the next step uses
+ * it.  EINVAL for an unknown kind. */
+enum { LBM_COLLISION_CHM_MRT = 0, LBM_COLLISION_SRT2 = 1 };
+int lbm_set_collision(lbm_domain* dom, int kind);
+
 /* Velocity inlet on the INLET ghost cells: the wall velocity of a link is
  * u_w = axis * U(r, t) at the link midpoint, where r is the distance from the
  * line through `center` along `axis` and U is the Womersley profile

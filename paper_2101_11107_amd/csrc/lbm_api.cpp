@@ -117,6 +117,7 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.partials = (double*)(base + d->off_part);
     a.avg = d->avg_track ? (double*)(base + d->off_avg) : nullptr;
     a.tin = d->cur;
+    a.collision = d->collision;
     a.n = (int)d->n;
     a.npad = d->npad;
     a.nx = d->nx;
@@ -242,7 +243,7 @@ int launch_steps_eager(lbm_domain* d, int nsteps) {
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
         const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(),
-                                 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES};
+                                 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES, d->collision == 1};
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
         d->cur ^= 1;
     }
@@ -710,6 +711,14 @@ int lbm_set_outlet_pressure(lbm_domain* d, double rho_out) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (!std::isfinite(rho_out) || !(rho_out > 0.0)) return fail(LBM_EINVAL, "rho_out must be finite and > 0");
     d->rho_out = rho_out;
+    d->drop_graphs();
+    return LBM_OK;
+}
+
+int lbm_set_collision(lbm_domain* d, int kind) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (kind != LBM_COLLISION_CHM_MRT && kind != LBM_COLLISION_SRT2) return fail(LBM_EINVAL, "unknown collision kind");
+    d->collision = kind;
     d->drop_graphs();
     return LBM_OK;
 }

@@ -25,16 +25,19 @@ __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int ste
         a.tin ^= 1;
     }
     const int lb = packed & ITEM_BLOCK_MASK;
-    // ONE: every domain of the batch has free rates of one.  Otherwise each
-    // item takes its own domain's collision form, as the domain's own step
-    // would (the two forms round differently).
-    const bool one = ONE || (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0);
+    // ONE: every domain of the batch is CHM-MRT with free rates of one.
+    // Otherwise each item takes its own domain's collision form, as the
+    // domain's own step would (the forms round differently).
+    const bool one = ONE || (a.collision == 0 && a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0);
     if (one) {
-        if (a.periodic & 6) step_block<S, MON, true, true, NT, BS>(a, lb);
-        else step_block<S, MON, true, false, NT, BS>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 1, true, NT, BS>(a, lb);
+        else step_block<S, MON, 1, false, NT, BS>(a, lb);
+    } else if (a.collision == 1) {
+        if (a.periodic & 6) step_block<S, MON, 2, true, NT, BS>(a, lb);
+        else step_block<S, MON, 2, false, NT, BS>(a, lb);
     } else {
-        if (a.periodic & 6) step_block<S, MON, false, true, NT, BS>(a, lb);
-        else step_block<S, MON, false, false, NT, BS>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 0, true, NT, BS>(a, lb);
+        else step_block<S, MON, 0, false, NT, BS>(a, lb);
     }
 }
 

@@ -87,6 +87,13 @@ __device__ inline double feq1(int a, double rho, const double u[3]) {
     return r;
 }
 
+// Second-order equilibrium (Eq. (3) cut after n = 2) in FP64, one direction.
+__device__ inline double feq2(int a, double rho, const double u[3]) {
+    const double cu = cxo(a) * u[0] + cyo(a) * u[1] + czo(a) * u[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return wgt(a) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
 // --- central Hermite transforms on one line (c = -1, 0, +1) ---------------------
 // Forward: (f-, f0, f+) -> (m0, m1, m2) with H0 = 1, H1 = c - u, H2 = (c - u)^2 - 1/3.
 template <class T>
@@ -489,9 +496,39 @@ __device__ __forceinline__ void block_monitor(double (&m)[9], double* __restrict
     __syncthreads();   // red may be reused by the block's next work item
 }
 
+// SRT comparator (Sec. 2.1.1-2.1.2): BGK relaxation (Eq. (2)) of the shifted
+// populations towards the equilibrium of Eq. (3) cut after its second-order
+// term, f_eq2 - w = w (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)), plus Guo's
+// force populations (1 - om/2) w rho [3 (c - u).g + 9 (c.u)(c.g)], om = 1/tau.
+template <class T>
+__device__ __forceinline__ void collide_srt2(T (&f)[27], T drho, T ux, T uy, T uz, T om, const T (&g)[3],
+                                             bool force) {
+    const T rho = T(1) + drho;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T ug = ux * g[0] + uy * g[1] + uz * g[2];
+    const T fo = (T(1) - T(0.5) * om) * rho;
+#pragma unroll
+    for (int al = 0; al < 27; ++al) {
+        const int cx = cxo(al), cy = cyo(al), cz = czo(al);
+        const T cu = (cx ? (cx > 0 ? ux : -ux) : T(0)) + (cy ? (cy > 0 ? uy : -uy) : T(0)) +
+                     (cz ? (cz > 0 ? uz : -uz) : T(0));
+        const T w = (T)wgt(al);
+        const T feq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
+        T v = f[al] - om * (f[al] - feq);
+        if (force) {
+            const T cg = (cx ? (cx > 0 ? g[0] : -g[0]) : T(0)) + (cy ? (cy > 0 ? g[1] : -g[1]) : T(0)) +
+                         (cz ? (cz > 0 ? g[2] : -g[2]) : T(0));
+            v += fo * w * (T(3) * (cg - ug) + T(9) * cu * cg);
+        }
+        f[al] = v;
+    }
+}
+
 // Collision of the gathered populations (in place): moments, then one of the
-// two collision forms.  Returns the velocity and the conserved sums.
-template <class T, bool ONE>
+// collision forms (FORM 0: CHM-MRT with general rates, 1: CHM-MRT with the
+// free rates one, 2: the SRT comparator).  Returns the velocity and the
+// conserved sums.
+template <class T, int FORM>
 __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T& uy, T& uz, T& drho,
                                         T& jx, T& jy, T& jz) {
     T S0[9], S1[9], S2[9];
@@ -506,8 +543,10 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
     ux = (jx + hr * g[0]) * inv;
     uy = (jy + hr * g[1]) * inv;
     uz = (jz + hr * g[2]) * inv;
-    if (ONE) {
+    if (FORM == 1) {
         collide_rates_one(f, S0, S1, S2, drho, jx, jy, jz, ux, uy, uz, hr, (T)(1.0 - a.s[0]), (T)a.s[0], g);
+    } else if (FORM == 2) {
+        collide_srt2(f, drho, ux, uy, uz, (T)a.s[0], g, a.g[0] != 0.0 || a.g[1] != 0.0 || a.g[2] != 0.0);
     } else {
         T om[5], sr[5];
 #pragma unroll
@@ -523,7 +562,7 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
 // Logical block lb of the domain (BS consecutive nodes).  Used by the
 // single-domain kernel and by the batched kernels, so a node's arithmetic is
 // the same in both.
-template <class S, bool MON, bool ONE, bool PER, bool NT, int BS>
+template <class S, bool MON, int FORM, bool PER, bool NT, int BS>
 __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
@@ -558,7 +597,7 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             F[2] -= 2.0 * (double)fz;
         }
         T ux, uy, uz, drho, jx, jy, jz;
-        collide<T, ONE>(f, a, ux, uy, uz, drho, jx, jy, jz);
+        collide<T, FORM>(f, a, ux, uy, uz, drho, jx, jy, jz);
         if (a.avg != nullptr) {
             // running sum of the velocity of every step (each node its own entries)
             LBM_GLOBAL double* avg = (LBM_GLOBAL double*)a.avg;

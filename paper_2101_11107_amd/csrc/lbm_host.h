@@ -107,7 +107,11 @@ struct lbm_domain {
         const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + k];
         return e.prefix + __builtin_popcount(e.bits & ((2u << r) - 1u));
     }
-    bool rates_one() const { return s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0; }
+    int collision = 0;                     // LBM_COLLISION_*
+    // the CHM-MRT form with every free rate equal to one (its specialized kernel)
+    bool rates_one() const {
+        return collision == 0 && s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0;
+    }
     bool periodic_yz() const { return (periodic & 6u) != 0; }
 };
 

@@ -73,6 +73,7 @@ struct StepArgs {
     double* partials;            // [nblocks][MON_WORDS] monitor partials
     double* avg;                 // [3][n] FP64 velocity sums the step adds to, or null
     int tin;
+    int collision;               // LBM_COLLISION_CHM_MRT or LBM_COLLISION_SRT2
     int n, npad, nx, ny, nz, W, periodic;
     int nblocks, blocks_per_xcd;
     double s[5];                 // relaxation rates of orders 2..6
@@ -89,6 +90,7 @@ struct StepVariant {
     bool rates_one;      // free rates of orders 3..6 all equal to 1
     bool periodic_yz;    // a periodic y or z axis (node words hold x, y, z)
     bool stream_store;   // non-temporal population stores (working set beyond the Infinity Cache)
+    bool srt2;           // the SRT comparator instead of CHM-MRT
 };
 
 // Several domains stepped by one launch.  Work item k of the launch is block

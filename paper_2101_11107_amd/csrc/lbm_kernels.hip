@@ -9,12 +9,12 @@ namespace {
 // One step over one domain.  XCD-aware order: hardware work-group b runs on
 // XCD (b % 8); each XCD gets a contiguous range of the node list, so
 // neighbouring rows share its L2.
-template <class S, bool MON, bool ONE, bool PER, bool NT>
+template <class S, bool MON, int FORM, bool PER, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
     const int hb = blockIdx.x;
     const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
     if (lb >= a.nblocks) return;
-    step_block<S, MON, ONE, PER, NT, BLOCK>(a, lb);
+    step_block<S, MON, FORM, PER, NT, BLOCK>(a, lb);
 }
 
 // Initial state: f(0) = f_eq(rho, u), then the first collision (written to
@@ -34,12 +34,15 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
     T f[27];
     // the rest state is exactly zero in shifted variables
 #pragma unroll
-    for (int al = 0; al < 27; ++al) f[al] = (rho0 || u0) ? (T)(feq1(al, r, u) - wgt(al)) : T(0);
+    for (int al = 0; al < 27; ++al)
+        f[al] = (rho0 || u0) ? (T)((a.collision == 1 ? feq2(al, r, u) : feq1(al, r, u)) - wgt(al)) : T(0);
     T ux, uy, uz, drho, jx, jy, jz;
-    if (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0)
-        collide<T, true>(f, a, ux, uy, uz, drho, jx, jy, jz);
+    if (a.collision == 1)
+        collide<T, 2>(f, a, ux, uy, uz, drho, jx, jy, jz);
+    else if (a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0)
+        collide<T, 1>(f, a, ux, uy, uz, drho, jx, jy, jz);
     else
-        collide<T, false>(f, a, ux, uy, uz, drho, jx, jy, jz);
+        collide<T, 0>(f, a, ux, uy, uz, drho, jx, jy, jz);
     const uint32_t w = a.node[i];
     if (w & SPECIAL_BIT) {
         const LBM_GLOBAL SpecialNode* sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
@@ -145,23 +148,24 @@ __global__ void k_fill_zero(uint32_t* p, size_t nwords) {
 // 6 x (26000 B + the monitor's static LDS) fits the CU's 160 KiB, 7 x does not.
 constexpr unsigned STEP_LDS_SIX_PER_CU = 26000;
 
-template <class S, bool MON, bool ONE, bool NT>
+template <class S, bool MON, int FORM, bool NT>
 hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
     const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
     const unsigned lds = (NT && sizeof(S) == 4) ? STEP_LDS_SIX_PER_CU : 0u;
-    if (per) hipLaunchKernelGGL((k_step<S, MON, ONE, true, NT>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_step<S, MON, ONE, false, NT>), grid, block, lds, st, a);
+    if (per) hipLaunchKernelGGL((k_step<S, MON, FORM, true, NT>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_step<S, MON, FORM, false, NT>), grid, block, lds, st, a);
     return hipGetLastError();
+}
+
+template <class S, bool MON, bool NT>
+hipError_t step_form(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.srt2) return step_per<S, MON, 2, NT>(a, v.periodic_yz, st);
+    return v.rates_one ? step_per<S, MON, 1, NT>(a, v.periodic_yz, st) : step_per<S, MON, 0, NT>(a, v.periodic_yz, st);
 }
 
 template <class S, bool NT>
 hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if (v.monitor) {
-        return v.rates_one ? step_per<S, true, true, NT>(a, v.periodic_yz, st)
-                           : step_per<S, true, false, NT>(a, v.periodic_yz, st);
-    }
-    return v.rates_one ? step_per<S, false, true, NT>(a, v.periodic_yz, st)
-                       : step_per<S, false, false, NT>(a, v.periodic_yz, st);
+    return v.monitor ? step_form<S, true, NT>(a, v, st) : step_form<S, false, NT>(a, v, st);
 }
 
 // Streaming stores only pay for 4- and 8-byte populations (measured); the

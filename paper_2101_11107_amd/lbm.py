@@ -28,7 +28,7 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
 EXPORTED = [
     "lbm_last_error", "lbm_create_domain", "lbm_create_domain_curved", "lbm_wall_links",
     "lbm_device_bytes", "lbm_attach_device",
-    "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_inlet_womersley",
+    "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_collision", "lbm_set_inlet_womersley",
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
     "lbm_average", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
     "lbm_inlet_profile", "lbm_destroy",
@@ -72,6 +72,7 @@ def load():
                                       _P, _P, ctypes.c_int64, _P, ctypes.POINTER(_P)], ctypes.c_int),
         "lbm_wall_links": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _P,
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lbm_set_collision": ([_P, ctypes.c_int], ctypes.c_int),
         "lbm_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
         "lbm_fluid_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -185,6 +186,14 @@ def lbm_wall_links(mask: np.ndarray, periodic_bits: int) -> np.ndarray:
         _check(load().lbm_wall_links(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits),
                                      out.ctypes.data_as(_P), ctypes.byref(cnt)))
     return out
+
+
+LBM_COLLISION_CHM_MRT, LBM_COLLISION_SRT2 = 0, 1
+COLLISION = {"chm_mrt": LBM_COLLISION_CHM_MRT, "srt2": LBM_COLLISION_SRT2}
+
+
+def lbm_set_collision(dom, kind) -> None:
+    _check(load().lbm_set_collision(dom, COLLISION[kind] if isinstance(kind, str) else int(kind)))
 
 
 def lbm_device_bytes(dom) -> int:
@@ -372,6 +381,7 @@ class Domain:
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         lbm_attach_device(self.handle, self.view)
         lbm_set_params(self.handle, case.tau, case.rates, case.g)
+        lbm_set_collision(self.handle, getattr(case, "collision", "chm_mrt"))
         if case.inlet is not None:
             i = case.inlet
             lbm_set_inlet_womersley(self.handle, i.axis, i.center, i.radius, i.G0, i.G1, i.omega)

@@ -1,0 +1,132 @@
+"""The SRT comparator on the GPU (Sec. 2.1.1-2.1.2): BGK relaxation towards the
+second-order EDF with Guo's force, through the C ABI, against the FP64 oracle.
+
+Bars as for the CHM-MRT step: FP64 storage within 1e-13 on populations
+(1e-12 relative on velocities), FP32 within 1e-5 relative.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import eps_u, gpu_run, moments_from_post, oracle_post
+
+pytestmark = pytest.mark.gpu
+
+
+def _srt(case):
+    return dataclasses.replace(case, collision="srt2")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 3, 4])
+def test_tiny_random_cases_f64_population_parity(seed):
+    """Walls, periodic axes, inlet and outlet ghosts and a body force."""
+    print(f"case srt tiny{seed} f64", flush=True)
+    case = _srt(synth.random_tiny_case(seed, nx=11, ny=9, nz=8))
+    dom, f = gpu_run(case, "f64", 20)
+    mon = dom.monitors()
+    dom.close()
+    sim, ref, _, _ = oracle_post(case, 20)
+    assert np.max(np.abs(f - ref)) < 1e-13
+    from oracle import o2
+    mref = o2.O2Sim(case, nthreads=4).run(20)
+    assert np.max(np.abs(mon - mref) / np.maximum(np.abs(mref), 1.0)) < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_tiny_random_case_reduced_storage(storage):
+    print(f"case srt tiny {storage}", flush=True)
+    case = _srt(synth.random_tiny_case(3, nx=11, ny=9, nz=8))
+    dom, f = gpu_run(case, storage, 20)
+    dom.close()
+    _, ref, _, _ = oracle_post(case, 20)
+    tol = 1e-5 if storage == "f32" else 2e-3
+    assert np.max(np.abs(f - ref)) < tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_pipe_poiseuille_2000_steps(storage, tol):
+    """The config-1 pipe driven at g = 1e-5 (u_max 2.5e-3): the oracle relaxes
+    unshifted populations (about 0.3), so each f - f_eq2 costs it about 1e-17
+    per population and step; at u_max 2.5e-4 that alone reaches 1e-12 of the
+    velocity in 2000 steps."""
+    print(f"case srt pipe {storage}", flush=True)
+    case = _srt(synth.pipe_case(g=1e-5))
+    dom, f = gpu_run(case, storage, 2000)
+    dom.close()
+    _, _, rho_ref, u_ref = oracle_post(case, 2000)
+    rho, u = moments_from_post(f, case.g)
+    assert eps_u(u, u_ref) < tol
+    assert np.max(np.abs(rho - rho_ref)) < tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_aneurysm256_prefix(storage, tol):
+    print(f"case srt aneurysm256 {storage}", flush=True)
+    case = _srt(synth.aneurysm_case(256, seed=0))
+    dom, f = gpu_run(case, storage, 300)
+    dom.close()
+    _, _, _, u_ref = oracle_post(case, 300)
+    _, u = moments_from_post(f, case.g)
+    assert eps_u(u, u_ref) < tol
+
+
+def test_initial_state_is_the_second_order_equilibrium():
+    """lbm_init_equilibrium with a velocity field starts an SRT domain from
+    the second-order EDF; ten steps then match the oracle started there."""
+    import torch
+    from oracle import o1_dense as o1
+    from oracle import o2
+    from paper_2101_11107_amd import lbm
+    print("case srt init", flush=True)
+    case = _srt(synth.periodic_box_case(12, 10, 8, tau=0.7, g=(1e-5, 0.0, 0.0)))
+    dom = lbm.Domain(case, storage="f64")
+    xyz = dom.coords()
+    rng = np.random.default_rng(3)
+    n = dom.n
+    rho = 1.0 + 0.01 * rng.standard_normal(n)
+    u = 0.02 * rng.standard_normal((3, n))
+    dom.init(torch.from_numpy(rho).cuda(), torch.from_numpy(np.ascontiguousarray(u)).cuda())
+    dom.step(10)
+    f = dom.populations().cpu().numpy().T
+    dom.close()
+    sim = o2.O2Sim(case, nthreads=4)
+    # library order -> oracle (x-fastest) order
+    nz, ny, nx = case.mask.shape
+    key = (xyz[:, 2].astype(np.int64) * ny + xyz[:, 1]) * nx + xyz[:, 0]
+    perm = np.argsort(key)
+    sim.f[...] = o1.equilibrium_second_order(rho[perm], u[:, perm].T)
+    sim.run(10)
+    sim.collide()
+    w = o2._weights()
+    assert np.max(np.abs(f[perm] - (sim.fpost - w[None, :]))) < 1e-13
+
+
+def test_mixed_batch_equals_solo():
+    """A batch of CHM-MRT (rates one and general rates) and SRT domains: each
+    domain bit-identical to stepping it alone."""
+    from paper_2101_11107_amd import lbm
+    cases = [synth.aneurysm_case(64, 1), _srt(synth.aneurysm_case(64, 2)),
+             synth.random_tiny_case(1, nx=31, ny=9, nz=8), _srt(synth.random_tiny_case(3, nx=31, ny=9, nz=8))]
+    steps = 37
+    for storage in ("f64", "f32"):
+        print(f"case srt batch {storage}", flush=True)
+        doms = [lbm.Domain(c, storage=storage) for c in cases]
+        for d in doms:
+            d.init()
+        b = lbm.Batch(doms)
+        b.step(steps)
+        b.status()
+        got = [d.populations().cpu().numpy() for d in doms]
+        b.close()
+        for d in doms:
+            d.close()
+        for c, fb in zip(cases, got):
+            d = lbm.Domain(c, storage=storage)
+            d.init()
+            d.step(steps)
+            fs = d.populations().cpu().numpy()
+            d.close()
+            assert np.array_equal(fb, fs)
