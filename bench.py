@@ -19,6 +19,7 @@ velocity error against the FP64 fine run beside the trilinear upsampling.
 """
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -344,6 +345,22 @@ def main():
             del ref
         also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, main_run))
         note(f"curved walls: {also[-1]['mlups']:.1f} MLUPS, pipe order {also[-1]['pipe_order']}")
+        # SRT comparator: its step rate on the same run, and the stability sweep
+        r = run_form(torch, lbm, dataclasses.replace(case, collision="srt2"), args.storage, args.warmup,
+                     args.steps)
+        also.append({"workload": f"{workload}_srt2", "storage": args.storage, "mlups": round(r["mlups"], 1),
+                     "roofline_frac": roofline(r["n"], r["ms_per_step"], args.storage, None)["frac"],
+                     "rate_vs_chm_mrt": round(r["mlups"] / main_run["mlups"], 3)})
+        note(f"srt2: {also[-1]['mlups']:.1f} MLUPS")
+        from paper_2101_11107_amd import stability
+        sw = stability.sweep(128, 0, "f32")
+        also.append({"workload": "stability_sweep_aneurysm128_steady_u0.06", "storage": "f32",
+                     "steps": sw["rows"][0]["steps"], "lowest_stable_tau": sw["lowest_stable_tau"],
+                     "rows": [{"tau": r["tau"], "fourier": r["fourier"],
+                               "chm_mrt": r["chm_mrt"]["status"], "srt2": r["srt2"]["status"],
+                               "srt2_failed_by_step": r["srt2"]["steps"] if r["srt2"]["status"] != "stable" else None}
+                              for r in sw["rows"]]})
+        note(f"stability: lowest stable tau {sw['lowest_stable_tau']}")
         also.append(batch_bench(torch, lbm, 480))
         note(f"batch: {also[-1]['batched_mlups']:.1f} MLUPS batched")
         if not args.no_corrector:

@@ -242,21 +242,27 @@ def _aneurysm_mask(n: int, seed: int, tube_radius: Optional[float] = None,
 
 def aneurysm_case(n: int = 256, seed: int = 0, period: Optional[int] = None,
                   tube_radius: Optional[float] = None, steps: Optional[int] = None,
-                  u_steady_centre: float = _U_STEADY_CENTRE) -> Case:
+                  u_steady_centre: float = _U_STEADY_CENTRE, tau: Optional[float] = None) -> Case:
     """Synthetic aneurysm in an n^3 box with a Womersley inlet and a zero-pressure outlet.
 
     Acoustic scaling (Sec. 3.4): all lengths scale with n/256, the period in
     steps scales with n/256 and the lattice velocity is unchanged, so tau - 1/2
     doubles when n doubles.  n = 256 gives tau = 0.575398 (period 4000),
     n = 512 gives tau = 0.650796 (period 8000), n = 128 gives 0.537699 (2000).
+    ``tau`` overrides the relaxation time at the same inlet speed.
     """
     mask, geo = _aneurysm_mask(n, seed, tube_radius)
     rt = geo["tube_radius"]
     if period is None:
         period = int(round(_PERIOD_256 * n / 256.0))
     omega = 2.0 * math.pi / period
-    nu = omega * rt * rt / (_WOMERSLEY_ALPHA ** 2)
-    tau = 0.5 + 3.0 * nu
+    if tau is None:
+        nu = omega * rt * rt / (_WOMERSLEY_ALPHA ** 2)
+        tau = 0.5 + 3.0 * nu
+    else:
+        # a given relaxation time (viscosity) at the same inlet speed; the
+        # Womersley number then follows from it
+        nu = (tau - 0.5) / 3.0
     G0 = 4.0 * nu * u_steady_centre / (rt * rt)
     inlet = Inlet(axis=(0.0, 1.0, 0.0), center=geo["inlet_center"], radius=rt,
                   G0=G0, G1=G0, omega=omega)

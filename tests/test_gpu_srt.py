@@ -130,3 +130,20 @@ def test_mixed_batch_equals_solo():
             fs = d.populations().cpu().numpy()
             d.close()
             assert np.array_equal(fb, fs)
+
+
+def test_coarse_run_chm_mrt_stable_where_srt_is_not():
+    """The paper's coarse run (Sec. 2.2.3): tau = 0.503 (Fo = 0.001) with a
+    steady inflow of peak lattice speed about 0.06.  CHM-MRT completes 4000
+    steps with bounded velocities; the SRT comparator blows up, and the
+    library reports it as LBM_EUNSTABLE (non-finite monitors) rather than
+    returning garbage."""
+    from paper_2101_11107_amd import stability
+    print("case stability tau 0.503", flush=True)
+    import synth as s
+    case = s.aneurysm_case(128, 0, tau=0.503, u_steady_centre=0.06)
+    case = dataclasses.replace(case, inlet=dataclasses.replace(case.inlet, G1=0.0, omega=0.0))
+    chm = stability.run_one(case, "chm_mrt", "f32", 4000)
+    srt = stability.run_one(case, "srt2", "f32", 4000)
+    assert chm["status"] == "stable" and chm["u_max"] < 0.1
+    assert srt["status"] in ("non-finite", "diverged") and srt["steps"] < 4000
