@@ -207,6 +207,25 @@ int lbm_moments(lbm_domain* dom, double* rho, double* u);
 enum { LBM_AVG_RESET = 0, LBM_AVG_ACCUMULATE = 1, LBM_AVG_READ = 2, LBM_AVG_TRACK = 3 };
 int lbm_average(lbm_domain* dom, int op, double* u_avg);
 
+/* Monitoring points (Sec. 2.2.2: the velocity at fixed points over several
+ * cycles shows when the flow has become periodic).  nprobe <= 64 fluid cells
+ * (x, y, z) = xyz[3k .. 3k+2] (host).  From the next step on, every step that
+ * forms a time t with t - t_set a positive multiple of `every` writes record
+ * r = (t - t_set) / every - 1 of the caller's device buffer
+ * out_dev double [capacity][nprobe][4] = (rho, ux, uy, uz) of each probe at
+ * time t: the values lbm_moments would report then, computed in the step
+ * kernel's arithmetic precision.  t_set is the time of the call (0 again
+ * after lbm_init_equilibrium).  Records beyond capacity are dropped.  out_dev
+ * must stay valid while probes are set; nprobe = 0 removes them.  Errors:
+ * EINVAL for a probe outside the box or not at a fluid cell, nprobe above 64,
+ * every or capacity below 1, NULL or misaligned buffers; ESTATE without
+ * device memory. */
+int lbm_set_probes(lbm_domain* dom, const int32_t* xyz, int nprobe, int every, double* out_dev,
+                   int64_t capacity);
+
+/* Records written so far (at most the capacity). */
+int lbm_probe_count(const lbm_domain* dom, int64_t* nrec);
+
 /* Monitors of the last step (host double[10]); synchronizes the stream.
  * out = { mass sum rho, momentum sum j (3), wall force (3), inlet mass flux,
  * outlet mass flux, t }.  The wall force is the momentum the walls receive,

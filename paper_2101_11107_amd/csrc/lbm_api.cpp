@@ -116,6 +116,12 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.sin_w = std::sin(d->omega);
     a.partials = (double*)(base + d->off_part);
     a.avg = d->avg_track ? (double*)(base + d->off_avg) : nullptr;
+    a.probe_node = (const int32_t*)(base + d->off_probe);
+    a.probe_out = d->probe_out;
+    a.probe_t0 = d->probe_t0;
+    a.probe_cap = d->probe_cap;
+    a.nprobe = d->nprobe;
+    a.probe_every = d->probe_every;
     a.tin = d->cur;
     a.collision = d->collision;
     a.n = (int)d->n;
@@ -530,6 +536,7 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->off_part = take((size_t)(npad / 64 + 1) * lbm::MON_WORDS * sizeof(double));
         d->off_monout = take(lbm::MON_WORDS * sizeof(double));
         d->off_avg = take((size_t)3 * nfluid * sizeof(double));
+        d->off_probe = take(lbm::MAX_PROBES * sizeof(int32_t));
         d->dev_bytes = off;
     } catch (const std::bad_alloc&) {
         delete d;
@@ -745,6 +752,10 @@ int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
         d->avg_track = false;
         d->drop_graphs();
     }
+    if (d->nprobe > 0 && d->probe_t0 != 0) {
+        d->probe_t0 = 0;   // records restart with the new run
+        d->drop_graphs();
+    }
     return LBM_OK;
 }
 
@@ -790,6 +801,44 @@ int lbm_moments(lbm_domain* d, double* rho, double* u) {
     if (!rho && !u) return LBM_OK;
     lbm::StepArgs a = make_args(d);
     HIP_TRY(lbm::launch_moments(d->storage, a, rho, u, nullptr, 0, 0.0, d->stream), "moments kernel");
+    return LBM_OK;
+}
+
+int lbm_set_probes(lbm_domain* d, const int32_t* xyz, int nprobe, int every, double* out_dev, int64_t capacity) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
+    if (nprobe < 0 || nprobe > lbm::MAX_PROBES) return fail(LBM_EINVAL, "nprobe must be in [0, 64]");
+    if (nprobe > 0) {
+        if (!xyz || !out_dev) return fail(LBM_EINVAL, "NULL argument");
+        if (every < 1 || capacity < 1) return fail(LBM_EINVAL, "every and capacity must be >= 1");
+        if (((uintptr_t)out_dev & 7u) != 0) return fail(LBM_EINVAL, "out_dev must be 8-byte aligned");
+    }
+    std::vector<int32_t> node((size_t)std::max(nprobe, 1), 0);
+    for (int k = 0; k < nprobe; ++k) {
+        const int x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+        if (x < 0 || x >= d->nx || y < 0 || y >= d->ny || z < 0 || z >= d->nz)
+            return fail(LBM_EINVAL, "probe outside the box");
+        if (!d->is_fluid(x, y, z)) return fail(LBM_EINVAL, "probe at a cell that is not fluid");
+        node[k] = d->index_of(x, y, z);
+    }
+    if (nprobe > 0)
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_probe, node.data(), (size_t)nprobe * sizeof(int32_t),
+                               hipMemcpyHostToDevice, d->stream), "upload of probe nodes");
+    // the host vector must outlive the copy
+    HIP_TRY(hipStreamSynchronize(d->stream), "probe upload");
+    d->nprobe = nprobe;
+    d->probe_every = nprobe > 0 ? every : 1;
+    d->probe_out = nprobe > 0 ? out_dev : nullptr;
+    d->probe_cap = nprobe > 0 ? capacity : 0;
+    d->probe_t0 = d->t;
+    d->drop_graphs();
+    return LBM_OK;
+}
+
+int lbm_probe_count(const lbm_domain* d, int64_t* nrec) {
+    if (!d || !nrec) return fail(LBM_EINVAL, "NULL argument");
+    *nrec = d->nprobe > 0 ? std::min<int64_t>(d->probe_cap, std::max<int64_t>(0, d->t - d->probe_t0) / d->probe_every)
+                          : 0;
     return LBM_OK;
 }
 

@@ -598,6 +598,25 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         }
         T ux, uy, uz, drho, jx, jy, jz;
         collide<T, FORM>(f, a, ux, uy, uz, drho, jx, jy, jz);
+        if (a.nprobe > 0) {
+            // monitoring points: the state this step forms is time tn
+            const int64_t dt = a.tcount[a.tin] + 1 - a.probe_t0;
+            if (dt > 0 && dt % a.probe_every == 0) {
+                const int64_t rec = dt / a.probe_every - 1;
+                if (rec < a.probe_cap) {
+                    const LBM_GLOBAL int32_t* pn = (const LBM_GLOBAL int32_t*)a.probe_node;
+                    for (int p = 0; p < a.nprobe; ++p) {
+                        if (pn[p] == i) {
+                            LBM_GLOBAL double* o = (LBM_GLOBAL double*)a.probe_out + (rec * a.nprobe + p) * 4;
+                            o[0] = 1.0 + (double)drho;
+                            o[1] = (double)ux;
+                            o[2] = (double)uy;
+                            o[3] = (double)uz;
+                        }
+                    }
+                }
+            }
+        }
         if (a.avg != nullptr) {
             // running sum of the velocity of every step (each node its own entries)
             LBM_GLOBAL double* avg = (LBM_GLOBAL double*)a.avg;

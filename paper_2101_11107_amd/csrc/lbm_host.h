@@ -72,7 +72,7 @@ struct lbm_domain {
     size_t dev_bytes = 0;
     size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
            off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0,
-           off_lwq = 0, off_loff2 = 0;
+           off_lwq = 0, off_loff2 = 0, off_probe = 0;
     size_t pop_bytes = 0;
 
     int cur = 0;
@@ -84,6 +84,10 @@ struct lbm_domain {
     int mon_blocks = 0;       // monitor partials written by that step
     int64_t avg_count = 0;
     bool avg_track = false;   // the step kernel adds u of every step to the accumulator
+    // monitoring points
+    int nprobe = 0, probe_every = 1;
+    double* probe_out = nullptr;
+    int64_t probe_t0 = 0, probe_cap = 0;
     double mon_host[lbm::MON_WORDS] = {0};
 
     // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer
@@ -102,6 +106,10 @@ struct lbm_domain {
     int row_of(int y, int z) const { return (z + 1) * (ny + 2) + (y + 1); }
     // index of the fluid node at (x, y, z) (must be fluid): prefix + popcount
     // of the entry's cells 30k - 1 .. x - 1
+    bool is_fluid(int x, int y, int z) const {
+        const int k = x / lbm::ROW_SPAN, r = x - k * lbm::ROW_SPAN;
+        return (rowtab[(size_t)row_of(y, z) * W + k].bits >> (r + 1)) & 1u;
+    }
     int32_t index_of(int x, int y, int z) const {
         const int k = x / lbm::ROW_SPAN, r = x - k * lbm::ROW_SPAN;
         const lbm::RowEntry& e = rowtab[(size_t)row_of(y, z) * W + k];

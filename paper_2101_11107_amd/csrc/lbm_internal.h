@@ -24,6 +24,7 @@ constexpr int MON_WORDS = 10;         // doubles per work-group monitor partial
 // list index of the row's first fluid cell at or after 30k - 1 (the number
 // of fluid nodes before it in list order).
 constexpr int ROW_SPAN = 30;          // cells per row-table entry
+constexpr int MAX_PROBES = 64;        // monitoring points of a domain
 struct alignas(8) RowEntry {
     uint32_t bits;
     int32_t prefix;
@@ -72,6 +73,10 @@ struct StepArgs {
     double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials
     double* avg;                 // [3][n] FP64 velocity sums the step adds to, or null
+    const int32_t* probe_node;   // [nprobe] node indices of the monitoring points
+    double* probe_out;           // [probe_cap][nprobe][4] (rho, ux, uy, uz) records, or null
+    int64_t probe_t0, probe_cap; // time the probes were set; records the buffer holds
+    int nprobe, probe_every;     // probes (0: none); record every probe_every steps
     int tin;
     int collision;               // LBM_COLLISION_CHM_MRT or LBM_COLLISION_SRT2
     int n, npad, nx, ny, nz, W, periodic;

@@ -30,7 +30,7 @@ EXPORTED = [
     "lbm_device_bytes", "lbm_attach_device",
     "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_collision", "lbm_set_inlet_womersley",
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
-    "lbm_average", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
+    "lbm_average", "lbm_set_probes", "lbm_probe_count", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
     "lbm_inlet_profile", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_device_bytes", "lbm_batch_attach_device", "lbm_batch_config",
     "lbm_batch_set_config", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_status", "lbm_batch_destroy",
@@ -73,6 +73,8 @@ def load():
         "lbm_wall_links": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _P,
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_set_collision": ([_P, ctypes.c_int], ctypes.c_int),
+        "lbm_set_probes": ([_P, _P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64], ctypes.c_int),
+        "lbm_probe_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_attach_device": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
         "lbm_fluid_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -438,6 +440,24 @@ class Domain:
 
     def set_state(self, blob):
         lbm_set_state(self.handle, blob)
+
+    def set_probes(self, xyz, every: int, capacity: int):
+        """Monitoring points: xyz int [k, 3]; records (rho, ux, uy, uz) every
+        ``every`` steps into a device tensor [capacity, k, 4] (returned)."""
+        t = self.torch
+        xyz = np.ascontiguousarray(xyz, np.int32).reshape(-1, 3)
+        self.probe_buf = t.zeros((int(capacity), len(xyz), 4), dtype=t.float64, device=self.device)
+        self._in()
+        _check(load().lbm_set_probes(self.handle, xyz.ctypes.data_as(_P), len(xyz), int(every),
+                                     _P(self.probe_buf.data_ptr()), int(capacity)))
+        return self.probe_buf
+
+    def probe_records(self):
+        """The records written so far: device tensor [count, k, 4]."""
+        n = ctypes.c_int64()
+        _check(load().lbm_probe_count(self.handle, ctypes.byref(n)))
+        self._out()
+        return self.probe_buf[: n.value]
 
     def monitors(self):
         return lbm_monitors(self.handle)

@@ -148,3 +148,16 @@ def test_curved_domain_validation_and_size():
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_create_domain_curved(case.mask, case.periodic, lbm.LBM_F64, lk, qq, 0)
         assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_probe_arguments_need_device_memory_and_fluid_cells():
+    lbm = _lbm()
+    case = synth.random_tiny_case(2, nx=11, ny=9, nz=8)
+    dom = lbm.lbm_create_domain(case.mask, case.periodic, lbm.LBM_F64, 0)
+    cnt = __import__("ctypes").c_int64(-1)
+    lbm._check(lbm.load().lbm_probe_count(dom, __import__("ctypes").byref(cnt)))
+    assert cnt.value == 0
+    xyz = np.array([[0, 0, 0]], np.int32)
+    rc = lbm.load().lbm_set_probes(dom, xyz.ctypes.data_as(lbm._P), 1, 1, lbm._P(64), 1)
+    assert rc == lbm.LBM_ESTATE          # no device memory attached yet
+    lbm.lbm_destroy(dom)
