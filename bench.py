@@ -361,6 +361,17 @@ def main():
                                "srt2_failed_by_step": r["srt2"]["steps"] if r["srt2"]["status"] != "stable" else None}
                               for r in sw["rows"]]})
         note(f"stability: lowest stable tau {sw['lowest_stable_tau']}")
+        from paper_2101_11107_amd import analysis
+        rs = analysis.resolution_study(seed=48, n=256, cycles=4, storage="f32")
+        also.append({"workload": "resolution_study_aneurysm256_vs_128", "storage": "f32", "cycles": 4,
+                     "plane_similarity_index": {p["plane"]: round(p["similarity_index"], 5) for p in rs["planes"]},
+                     "plane_points": {p["plane"]: p["points"] for p in rs["planes"]},
+                     "si_histograms": {p["plane"]: p["si_histogram"] for p in rs["planes"]},
+                     "probe_change_per_cycle_high": rs["periodicity_high"],
+                     "probe_change_per_cycle_low": rs["periodicity_low"],
+                     "seconds_high": rs["seconds_high"], "seconds_low": rs["seconds_low"],
+                     "cost_ratio": rs["cost_ratio"]})
+        note(f"resolution study: SI {also[-1]['plane_similarity_index']}, cost ratio {rs['cost_ratio']}")
         also.append(batch_bench(torch, lbm, 480))
         note(f"batch: {also[-1]['batched_mlups']:.1f} MLUPS batched")
         if not args.no_corrector:

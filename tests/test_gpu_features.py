@@ -238,3 +238,18 @@ def test_tracked_average_through_batch_equals_solo():
         d.close()
     for g, r in zip(got, ref):
         assert np.array_equal(g, r)
+
+
+def test_resolution_study_runs_and_is_consistent():
+    """The resolution study on a small geometry (128^3 against 64^3, two
+    periods): three planes with a similarity index in (0, 1], probe changes
+    for the second period, and a coarse run cheaper than the fine one."""
+    from paper_2101_11107_amd import analysis
+    print("case resolution study 128/64", flush=True)
+    res = analysis.resolution_study(seed=3, n=128, cycles=2)
+    assert len(res["planes"]) == 3
+    for p in res["planes"]:
+        assert p["points"] > 0 and 0.0 < p["similarity_index"] <= 1.0
+        assert abs(sum(p["si_histogram"]) - 1.0) < 1e-4     # entries rounded to 5 decimals
+    assert len(res["periodicity_high"]) == 1 and len(res["periodicity_low"]) == 1
+    assert res["fluid_nodes_high"] > 6 * res["fluid_nodes_low"]
