@@ -253,3 +253,24 @@ def test_resolution_study_runs_and_is_consistent():
         assert abs(sum(p["si_histogram"]) - 1.0) < 1e-4     # entries rounded to 5 decimals
     assert len(res["periodicity_high"]) == 1 and len(res["periodicity_low"]) == 1
     assert res["fluid_nodes_high"] > 6 * res["fluid_nodes_low"]
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.5])
+def test_wall_position_fixed_by_the_third_order_rate(tau):
+    """The oracle's pin P12 on the GPU (the general-rate CHM-MRT kernel, FP64):
+    with (1/s2 - 1/2)(1/s3 - 1/2) = 3/16 the steady channel profile with
+    halfway walls is exact to rounding."""
+    import dataclasses
+    from paper_2101_11107_amd import lbm
+    print(f"case channel wall position tau {tau}", flush=True)
+    H, g = 8, 1e-6
+    s3 = 1.0 / (0.5 + 0.1875 / (tau - 0.5))
+    case = dataclasses.replace(synth.channel_case(4, H + 2, 2, tau, g), rates=(s3, 1.0, 1.0, 1.0))
+    dom = lbm.Domain(case, storage="f64")
+    dom.init()
+    dom.step(int(40 * H * H / case.nu))
+    _, u = dom.moments()
+    y = dom.coords()[:, 1].astype(float)
+    dom.close()
+    ua = g / (2 * case.nu) * (y - 0.5) * (H + 0.5 - y)
+    assert np.abs(u.cpu().numpy()[0] - ua).max() / ua.max() < 1e-9

@@ -161,3 +161,18 @@ def test_probe_arguments_need_device_memory_and_fluid_cells():
     rc = lbm.load().lbm_set_probes(dom, xyz.ctypes.data_as(lbm._P), 1, 1, lbm._P(64), 1)
     assert rc == lbm.LBM_ESTATE          # no device memory attached yet
     lbm.lbm_destroy(dom)
+
+
+def test_unit_conversion_reproduces_the_papers_tau_pair():
+    """Sec. 2.2.3 prints tau = 0.506 (dx 1e-4 m, dt 5e-6 s) and 0.503 (2e-4 m,
+    1e-5 s).  Its stated nu = 3.2e-6 m^2/s gives 0.5048 instead; nu = 4e-6
+    reproduces both printed values and the acoustic halving of tau - 1/2.  The
+    quoted peak lattice speed 0.064 is 2.5 times the mean 0.512 m/s."""
+    from paper_2101_11107_amd import units
+    assert abs(units.lattice_tau(3.2e-6, 1e-4, 5e-6) - 0.5048) < 1e-12
+    assert abs(units.lattice_tau(4.0e-6, 1e-4, 5e-6) - 0.506) < 1e-12
+    assert abs(units.lattice_tau(4.0e-6, 2e-4, 1e-5) - 0.503) < 1e-12
+    assert abs(units.acoustic_coarsen(0.506) - 0.503) < 1e-12
+    assert abs(units.lattice_velocity(0.512, 1e-4, 5e-6) * 2.5 - 0.064) < 1e-12
+    assert abs(units.fourier(4.0e-6, 2e-4, 1e-5) - 0.001) < 1e-15
+    assert abs(units.physical_viscosity(0.506, 1e-4, 5e-6) - 4.0e-6) < 1e-18

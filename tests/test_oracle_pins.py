@@ -549,3 +549,30 @@ def test_P20_srt_dense_and_fast_oracles_agree(o2lib, seed):
     fl = st.fluid
     assert np.max(np.abs(st.f[fl[:, 0], fl[:, 1], fl[:, 2]] - sim.f)) < 1e-13
     assert np.max(np.abs(st.monitors - sim.monitors)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P12: wall position of halfway bounce-back (Sec. 2.1.2-2.1.3)
+# ---------------------------------------------------------------------------
+
+def _channel_error(o2lib, tau, s3, H=8, g=1e-6):
+    c = dataclasses.replace(synth.channel_case(4, H + 2, 2, tau, g), rates=(s3, 1.0, 1.0, 1.0))
+    nu = c.nu
+    sim = o2lib.O2Sim(c, nthreads=4)
+    sim.run(int(40 * H * H / nu))
+    _, u = sim.macroscopic()
+    y = sim.coords[:, 1].astype(float)
+    ua = g / (2 * nu) * (y - 0.5) * (H + 0.5 - y)      # walls halfway between nodes
+    return float(np.abs(u[:, 0] - ua).max() / ua.max())
+
+
+def test_P12_free_third_order_rate_fixes_the_wall_position(o2lib):
+    """With SRT-like rates the halfway wall sits at a tau-dependent place, the
+    shortcoming Sec. 2.1.2 recalls; CHM-MRT's free rates give the degree of
+    freedom to fix it (Sec. 2.1.3).  With (1/s2 - 1/2)(1/s3 - 1/2) = 3/16
+    steady channel Poiseuille flow is exact to rounding for every tau, while
+    s3 = 1 leaves a tau-dependent slip error."""
+    for tau in (0.6, 0.9, 1.5):
+        s3 = 1.0 / (0.5 + 0.1875 / (tau - 0.5))
+        assert _channel_error(o2lib, tau, s3) < 1e-9
+        assert _channel_error(o2lib, tau, 1.0) > 5e-4
