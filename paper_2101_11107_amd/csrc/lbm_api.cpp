@@ -250,6 +250,12 @@ int launch_steps_eager(lbm_domain* d, int nsteps) {
         lbm::StepArgs a = make_args(d);
         const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(),
                                  2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES, d->collision == 1};
+        if (!d->pre.empty())
+            HIP_TRY(lbm::launch_curved_pre(d->storage, const_cast<void*>(a.fin),
+                                           (const lbm::CurvedLink*)(d->dev + d->off_pre), (int64_t)d->pre.size(),
+                                           v.monitor ? a.partials + (size_t)d->nblocks * lbm::MON_WORDS : nullptr,
+                                           d->stream),
+                    "curved-wall pass");
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
         d->cur ^= 1;
     }
@@ -380,6 +386,41 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         const bool per[3] = {(periodic_bits & 1) != 0, (periodic_bits & 2) != 0, (periodic_bits & 4) != 0};
         const bool per_yz = per[1] || per[2];
         int64_t i = 0;
+        // Curved-wall link of node i at (x, y, z), incoming direction a, abar =
+        // 26 - a towards the wall (Eq. (9)-(10), linear interpolation):
+        //   q <  1/2: 2q f*_abar(x) + (1 - 2q) f*_abar(x + c_a)
+        //   q >= 1/2: f*_abar(x) / 2q + (2q - 1) / 2q f*_a(x)
+        // where x + c_a (the node behind x) must be fluid, else the link keeps
+        // halfway bounce-back (weights 1, 0).  Returns the weights and the
+        // plane and node of the second value.
+        auto curved_weights = [&](int x, int y, int z, int64_t node, int a, double& w0, double& w1,
+                                  int64_t& node2, int& plane2) {
+            const double q = wq->at(d->cell(x, y, z) * 27 + a);
+            w0 = 1.0;
+            w1 = 0.0;
+            node2 = node;
+            plane2 = 26 - a;
+            if (q >= 0.5) {
+                w0 = 1.0 / (2.0 * q);
+                w1 = (2.0 * q - 1.0) / (2.0 * q);
+                plane2 = a;
+                return;
+            }
+            const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+            int b[3] = {x + c[0], y + c[1], z + c[2]};
+            bool in = true;
+            for (int ax = 0; ax < 3; ++ax) {
+                if (b[ax] < 0 || b[ax] >= dims[ax]) {
+                    if (per[ax]) b[ax] = (b[ax] + dims[ax]) % dims[ax];
+                    else in = false;
+                }
+            }
+            if (in && mask[d->cell(b[0], b[1], b[2])] == LBM_FLUID) {
+                w0 = 2.0 * q;
+                w1 = 1.0 - 2.0 * q;
+                node2 = d->index_of(b[0], b[1], b[2]);
+            }
+        };
         for (int r : order) {
             const int z = r / (ny + 2) - 1, y = r % (ny + 2) - 1;
             for (int x = 0; x < nx; ++x) {
@@ -390,6 +431,7 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                     // classify the 27 sources x - c_alpha
                     int kind[27], sx[27], sy[27], sz[27];
                     bool special = false;
+                    uint32_t curved = 0;   // incoming directions with a wall distance
                     for (int a = 0; a < 27; ++a) {
                         const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
                         int q[3] = {x - c[0], y - c[1], z - c[2]};
@@ -410,12 +452,35 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                         sz[a] = q[2];
                         if (kind[a] == LBM_INLET || kind[a] == LBM_OUTLET) special = true;
                         if (xwrap && kind[a] == LBM_FLUID) special = true;
-                        if (wq && kind[a] == LBM_SOLID && wq->count(d->cell(x, y, z) * 27 + a)) special = true;
+                        if (wq && kind[a] == LBM_SOLID && wq->count(d->cell(x, y, z) * 27 + a)) curved |= 1u << a;
+                    }
+                    // Curved links of an ordinary node go to the pass before the
+                    // step, which rewrites f*_abar(x) of each in place.  A link
+                    // with q >= 1/2 reads f*_a(x), which that pass rewrites when
+                    // the link of direction abar is curved too (a one-cell gap):
+                    // such nodes take the explicit-offset path.
+                    if (curved && !special) {
+                        for (int a = 0; a < 27; ++a)
+                            if (((curved >> a) & 1u) && ((curved >> (26 - a)) & 1u) &&
+                                wq->at(d->cell(x, y, z) * 27 + a) >= 0.5)
+                                special = true;
                     }
                     if (d->index_of(x, y, z) != i) return fail(LBM_EINVAL, "internal: index mismatch");
                     if (!special) {
                         d->node_words[i] = per_yz ? ((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20))
                                                   : ((uint32_t)x | ((uint32_t)d->row_of(y, z) << 10));
+                        for (int a = 0; a < 27; ++a) {
+                            if (!((curved >> a) & 1u)) continue;
+                            lbm::CurvedLink cl{};
+                            int64_t node2;
+                            int plane2;
+                            curved_weights(x, y, z, i, a, cl.w0, cl.w1, node2, plane2);
+                            cl.dst = (uint32_t)i;            // element indices; bytes once the layout is fixed
+                            cl.src2 = (uint32_t)node2;
+                            cl.dir = a;
+                            d->pre.push_back(cl);
+                            d->pre_src_plane.push_back(plane2);
+                        }
                     } else {
                         SpecialNode sp{};
                         sp.node = (int32_t)i;
@@ -457,30 +522,10 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                         // link keeps halfway bounce-back (weights 1, 0).
                         for (int a = 0; a < 27; ++a) {
                             if (!((sp.qmask >> a) & 1u)) continue;
-                            const double q = wq->at(d->cell(x, y, z) * 27 + a);
-                            double w0 = 1.0, w1 = 0.0;
-                            int64_t node2 = i;
-                            int plane2 = 26 - a;
-                            if (q >= 0.5) {
-                                w0 = 1.0 / (2.0 * q);
-                                w1 = (2.0 * q - 1.0) / (2.0 * q);
-                                plane2 = a;
-                            } else {
-                                const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
-                                int b[3] = {x + c[0], y + c[1], z + c[2]};
-                                bool in = true;
-                                for (int ax = 0; ax < 3; ++ax) {
-                                    if (b[ax] < 0 || b[ax] >= dims[ax]) {
-                                        if (per[ax]) b[ax] = (b[ax] + dims[ax]) % dims[ax];
-                                        else in = false;
-                                    }
-                                }
-                                if (in && mask[d->cell(b[0], b[1], b[2])] == LBM_FLUID) {
-                                    w0 = 2.0 * q;
-                                    w1 = 1.0 - 2.0 * q;
-                                    node2 = d->index_of(b[0], b[1], b[2]);
-                                }
-                            }
+                            double w0, w1;
+                            int64_t node2;
+                            int plane2;
+                            curved_weights(x, y, z, i, a, w0, w1, node2, plane2);
                             d->link_meta.push_back(lbm::LINK_WALL_Q | (a << 8));
                             d->link_xyz.push_back(x);
                             d->link_xyz.push_back(y);
@@ -515,6 +560,18 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
             }
         d->spec_plane.clear();
         d->spec_plane.shrink_to_fit();
+        for (size_t k = 0; k < d->pre.size(); ++k) {
+            lbm::CurvedLink& cl = d->pre[k];
+            cl.dst = (uint32_t)(((uint64_t)(26 - cl.dir) * (uint64_t)npad + cl.dst) * sb);
+            cl.src2 = (uint32_t)(((uint64_t)d->pre_src_plane[k] * (uint64_t)npad + cl.src2) * sb);
+        }
+        d->pre_src_plane.clear();
+        d->pre_src_plane.shrink_to_fit();
+        // plane by plane, node order inside a plane: neighbouring threads then
+        // touch neighbouring populations (the links are independent)
+        std::sort(d->pre.begin(), d->pre.end(),
+                  [](const lbm::CurvedLink& p, const lbm::CurvedLink& q) { return p.dst < q.dst; });
+        d->pre_blocks = (int)((d->pre.size() + lbm::BLOCK - 1) / lbm::BLOCK);
         for (size_t k = 0; k < d->link_off2.size(); ++k)
             d->link_off2[k] = (uint32_t)(((uint64_t)d->link_off2_plane[k] * (uint64_t)npad + d->link_off2[k]) * sb);
         d->link_off2_plane.clear();
@@ -533,10 +590,11 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->off_tcount = take(2 * sizeof(int64_t));
         d->off_trig = take(4 * sizeof(double));
         // monitor partials: one per work-group, for work-groups down to 64 nodes
-        d->off_part = take((size_t)(npad / 64 + 1) * lbm::MON_WORDS * sizeof(double));
+        d->off_part = take((size_t)(npad / 64 + 1 + d->pre_blocks) * lbm::MON_WORDS * sizeof(double));
         d->off_monout = take(lbm::MON_WORDS * sizeof(double));
         d->off_avg = take((size_t)3 * nfluid * sizeof(double));
         d->off_probe = take(lbm::MAX_PROBES * sizeof(int32_t));
+        d->off_pre = take(std::max<size_t>(1, d->pre.size()) * sizeof(lbm::CurvedLink));
         d->dev_bytes = off;
     } catch (const std::bad_alloc&) {
         delete d;
@@ -648,6 +706,9 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     if (!d->spec.empty())
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_spec, d->spec.data(), d->spec.size() * sizeof(SpecialNode),
                                hipMemcpyHostToDevice, st), "upload of special nodes");
+    if (!d->pre.empty())
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_pre, d->pre.data(), d->pre.size() * sizeof(lbm::CurvedLink),
+                               hipMemcpyHostToDevice, st), "upload of curved-wall links");
     if (d->nlinks()) {
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_lmeta, d->link_meta.data(), d->nlinks() * sizeof(int32_t),
                                hipMemcpyHostToDevice, st), "upload of link table");
@@ -883,7 +944,8 @@ int lbm_monitors(lbm_domain* d, double out[10]) {
     if (!d || !out) return fail(LBM_EINVAL, "NULL argument");
     if (!d->monitored) return fail(LBM_ESTATE, "no step has run since initialisation");
     double* mo = (double*)(d->dev + d->off_monout);
-    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->mon_blocks, mo, d->stream),
+    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->mon_blocks + d->pre_blocks, mo,
+                                         d->stream),
             "monitor reduction");
     HIP_TRY(hipMemcpyAsync(d->mon_host, mo, 9 * sizeof(double), hipMemcpyDeviceToHost, d->stream), "monitor copy");
     HIP_TRY(hipStreamSynchronize(d->stream), "stream synchronize");

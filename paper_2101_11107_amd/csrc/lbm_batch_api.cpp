@@ -146,9 +146,23 @@ int enqueue_steps(lbm_batch* b, int g, int nsteps) {
                 "batch step kernel");
         return LBM_OK;
     }
-    for (int s = 0; s < nsteps; ++s)
+    for (int s = 0; s < nsteps; ++s) {
+        // curved-wall passes of the group's domains on the populations this step reads
+        for (int k = b->group_first[g]; k < b->group_first[g + 1]; ++k) {
+            const lbm_domain* d = b->doms[k];
+            if (d->pre.empty()) continue;
+            const lbm::StepArgs& da = b->args_host[k];
+            void* fin = const_cast<void*>((s & 1) ? (const void*)da.fout : da.fin);
+            const int rows = (int)((d->n + b->cfg.block - 1) / b->cfg.block);
+            HIP_TRY(lbm::launch_curved_pre(d->storage, fin, (const lbm::CurvedLink*)(d->dev + d->off_pre),
+                                           (int64_t)d->pre.size(),
+                                           s == nsteps - 1 ? da.partials + (size_t)rows * lbm::MON_WORDS : nullptr,
+                                           b->stream),
+                    "curved-wall pass");
+        }
         HIP_TRY(lbm::launch_batch_step(b->storage, b->rates_one, a, b->cfg, s, s == nsteps - 1, b->stream),
                 "batch step kernel");
+    }
     return LBM_OK;
 }
 
@@ -213,8 +227,16 @@ int run_steps(lbm_batch* b, int nsteps) {
     return LBM_OK;
 }
 
+bool has_curved_pass(const lbm_batch* b) {
+    for (const lbm_domain* d : b->doms)
+        if (!d->pre.empty()) return true;
+    return false;
+}
+
 bool valid_config(const lbm_batch* b, const lbm::BatchConfig& c) {
     if (c.mode != 0 && c.mode != 1) return false;
+    // the persistent kernel has no place for the curved-wall pass between steps
+    if (c.mode == 1 && has_curved_pass(b)) return false;
     if (c.block != 128 && c.block != 256 && c.block != 512) return false;
     if (c.stream_store != 0 && c.stream_store != 1) return false;
     if (c.stream_store && b->storage >= LBM_F16S) return false;
@@ -334,7 +356,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end() && !best_ms_per_step) {
+        if (it != g_tune_cache.end() && !best_ms_per_step && valid_config(b, it->second)) {
             b->cfg = it->second;
             return LBM_OK;
         }
@@ -346,7 +368,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
                 for (int ns : {0, 1}) {
                     if (ns && b->storage >= LBM_F16S) continue;
                     if (mode == 0) cands.push_back({0, block, ns, 0, group_mb});
-                    else {
+                    else if (!has_curved_pass(b)) {
                         cands.push_back({1, block, ns, 0, group_mb});
                         cands.push_back({1, block, ns, -2, group_mb});   // half of the resident capacity
                     }

@@ -50,6 +50,22 @@ static_assert(sizeof(SpecialNode) == 128, "special node record is 128 bytes");
 
 enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3, LINK_WALL_Q = 4 };
 
+// Curved-wall link of an ordinary node (Eq. (9)-(10)).  The population that
+// bounces back at a wall link, f*_abar(x) with abar = 26 - dir, is read by no
+// other node (its streaming destination is the wall), so a pass before the
+// step replaces it in place by w0 f*_abar(x) + w1 f2, which the bitmap path
+// then pulls as its ordinary bounce-back value.  dst, src2: byte offsets
+// (from the population buffer) of f*_abar(x) and f2; dir: the incoming
+// direction of the link.
+struct alignas(8) CurvedLink {
+    uint32_t dst;
+    uint32_t src2;
+    int32_t dir;
+    int32_t pad;
+    double w0, w1;
+};
+static_assert(sizeof(CurvedLink) == 32, "curved-wall record is 32 bytes");
+
 // Per open-boundary link: meta = type | alpha << 8; coef = (a0, a1re, a1im,
 // k1, k3, k5): the inlet speed at the link midpoint is
 // U = a0 + a1re cos(omega t) - a1im sin(omega t), and the moving-wall term
@@ -125,6 +141,10 @@ struct BatchConfig {
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream);
+// Curved-wall pass before a step on the populations `fin` it will read;
+// partials: nullptr, or the monitor rows of its wall-force correction.
+hipError_t launch_curved_pre(int storage, void* fin, const CurvedLink* links, int64_t n, double* partials,
+                             hipStream_t stream);
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream);
 hipError_t launch_moments(int storage, const StepArgs& a, double* rho, double* u, double* avg,

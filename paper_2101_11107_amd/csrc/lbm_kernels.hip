@@ -134,6 +134,36 @@ __global__ __launch_bounds__(BLOCK) void k_mon_final(const double* __restrict__ 
     if (threadIdx.x < 9) out[threadIdx.x] = sh[0][threadIdx.x];
 }
 
+// One curved-wall link per thread: f*_abar(x) <- w0 f*_abar(x) + w1 f2 (the
+// links of one launch write distinct places and read no place another writes;
+// the host keeps nodes where that would fail on the explicit-offset path).
+// With MON, the wall-force correction of the link: the step counts
+// 2 (f_new + w) c_abar for a wall link, momentum exchange wants
+// (f*_abar + f_new + 2 w) c_abar, so this adds (f*_abar - f_new) c_abar.
+template <class S, bool MON>
+__global__ __launch_bounds__(BLOCK) void k_curved_pre(char* __restrict__ fin, const CurvedLink* __restrict__ links,
+                                                      int64_t n, double* __restrict__ partials) {
+    using T = typename Traits<S>::T;
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (k < n) {
+        const LBM_GLOBAL CurvedLink* r = (const LBM_GLOBAL CurvedLink*)links + k;
+        LBM_GLOBAL char* base = (LBM_GLOBAL char*)fin;
+        const uint32_t dst = r->dst;
+        const T own = ldp<S>(base, dst);
+        const T v = (T)r->w0 * own + (T)r->w1 * ldp<S>(base, r->src2);
+        stp<S>(base, dst, v);
+        if (MON) {
+            const int al = r->dir;
+            const double d = (double)own - (double)v;   // c_abar = -c_al
+            mon[4] = -d * (double)(al % 3 - 1);
+            mon[5] = -d * (double)((al / 3) % 3 - 1);
+            mon[6] = -d * (double)(al / 9 - 1);
+        }
+    }
+    if (MON) block_monitor<BLOCK>(mon, partials + (size_t)blockIdx.x * MON_WORDS);
+}
+
 __global__ void k_fill_zero(uint32_t* p, size_t nwords) {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords;
          k += (size_t)gridDim.x * blockDim.x)
@@ -207,6 +237,20 @@ hipError_t readpop_t(const StepArgs& a, double* out, hipStream_t st) {
         case 3: return FN<__bf16>(__VA_ARGS__);                         \
         default: return hipErrorInvalidValue;                           \
     }
+
+template <class S>
+hipError_t curved_pre_t(void* fin, const CurvedLink* links, int64_t n, double* partials, hipStream_t st) {
+    const dim3 grid((unsigned)((n + BLOCK - 1) / BLOCK)), block(BLOCK);
+    if (partials) hipLaunchKernelGGL((k_curved_pre<S, true>), grid, block, 0, st, (char*)fin, links, n, partials);
+    else hipLaunchKernelGGL((k_curved_pre<S, false>), grid, block, 0, st, (char*)fin, links, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_curved_pre(int storage, void* fin, const CurvedLink* links, int64_t n, double* partials,
+                             hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, curved_pre_t, fin, links, n, partials, stream);
+}
 
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream) {
     LBM_DISPATCH(storage, step_t, a, v, stream);
