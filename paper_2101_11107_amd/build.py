@@ -11,7 +11,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_batch.hip", "lbm_net.hip", "lbm_api.cpp", "lbm_batch_api.cpp", "lbm_net_api.cpp"]
+# (source, extra flags, object name): the batch kernels compile once per
+# storage type, in parallel
+SOURCES = [("lbm_kernels.hip", [], "lbm_kernels"), ("lbm_net.hip", [], "lbm_net"),
+           *[("lbm_batch.hip", [f"-DLBM_BATCH_STORAGE={k}"], f"lbm_batch_{k}") for k in range(4)],
+           ("lbm_api.cpp", [], "lbm_api"), ("lbm_batch_api.cpp", [], "lbm_batch_api"),
+           ("lbm_net_api.cpp", [], "lbm_net_api")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -30,10 +35,10 @@ def build(verbose: bool = False) -> str:
     tmpdir = tempfile.mkdtemp(prefix="lbm_build_")
     objs = []
     cmds = []
-    for src in SOURCES:
-        obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
+    for src, extra, name in SOURCES:
+        obj = os.path.join(tmpdir, name + ".o")
         objs.append(obj)
-        cmds.append([HIPCC, *FLAGS, "-c", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *FLAGS, *extra, "-c", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, src), "-o", obj])
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(cmds)) as ex:
         results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
     for cmd, res in zip(cmds, results):

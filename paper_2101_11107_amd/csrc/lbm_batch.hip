@@ -8,6 +8,8 @@
 // domain's populations are bit-identical to stepping it alone.
 #include "lbm_device.h"
 
+#include <type_traits>
+
 namespace lbm {
 namespace {
 
@@ -201,27 +203,37 @@ hipError_t persistent_s(bool one, const BatchArgs& b, const BatchConfig& c, int 
 
 }  // namespace
 
-#define LBM_DISPATCH_S(storage, FN, ...)                                \
-    switch (storage) {                                                  \
-        case 0: return FN<double>(__VA_ARGS__);                         \
-        case 1: return FN<float>(__VA_ARGS__);                          \
-        case 2: return FN<_Float16>(__VA_ARGS__);                       \
-        case 3: return FN<__bf16>(__VA_ARGS__);                         \
-        default: return hipErrorInvalidValue;                           \
-    }
+// One storage type per translation unit (LBM_BATCH_STORAGE = 0 f64, 1 f32,
+// 2 f16s, 3 bf16s), so the four instantiations compile in parallel.
+#if !defined(LBM_BATCH_STORAGE)
+#error "compile with -DLBM_BATCH_STORAGE=0..3"
+#elif LBM_BATCH_STORAGE == 0
+#define LBM_BATCH_T double
+#elif LBM_BATCH_STORAGE == 1
+#define LBM_BATCH_T float
+#elif LBM_BATCH_STORAGE == 2
+#define LBM_BATCH_T _Float16
+#else
+#define LBM_BATCH_T __bf16
+#endif
 
-hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
-                             bool monitor, hipStream_t stream) {
-    LBM_DISPATCH_S(storage, step_s, rates_one, b, c, step, monitor, stream);
+hipError_t launch_batch_step_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+                               bool monitor, hipStream_t stream, std::integral_constant<int, LBM_BATCH_STORAGE>) {
+    (void)storage;
+    return step_s<LBM_BATCH_T>(rates_one, b, c, step, monitor, stream);
 }
 
-hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
-                                   int step0, int nsteps, hipStream_t stream) {
-    LBM_DISPATCH_S(storage, persistent_s, rates_one, b, c, step0, nsteps, stream);
+hipError_t launch_batch_persistent_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+                                     int step0, int nsteps, hipStream_t stream,
+                                     std::integral_constant<int, LBM_BATCH_STORAGE>) {
+    (void)storage;
+    return persistent_s<LBM_BATCH_T>(rates_one, b, c, step0, nsteps, stream);
 }
 
-hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks) {
-    LBM_DISPATCH_S(storage, capacity_s, rates_one, c, blocks);
+hipError_t batch_persistent_capacity_s(int storage, bool rates_one, const BatchConfig& c, int* blocks,
+                                       std::integral_constant<int, LBM_BATCH_STORAGE>) {
+    (void)storage;
+    return capacity_s<LBM_BATCH_T>(rates_one, c, blocks);
 }
 
 }  // namespace lbm

@@ -425,3 +425,32 @@ int lbm_batch_status(lbm_batch* b) {
 void lbm_batch_destroy(lbm_batch* b) { delete b; }
 
 }  // extern "C"
+
+namespace lbm {
+
+#define LBM_BATCH_SWITCH(FN, ...)                                                     \
+    switch (storage) {                                                                \
+        case 0: return FN(storage, __VA_ARGS__, std::integral_constant<int, 0>());    \
+        case 1: return FN(storage, __VA_ARGS__, std::integral_constant<int, 1>());    \
+        case 2: return FN(storage, __VA_ARGS__, std::integral_constant<int, 2>());    \
+        case 3: return FN(storage, __VA_ARGS__, std::integral_constant<int, 3>());    \
+        default: return hipErrorInvalidValue;                                         \
+    }
+
+hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+                             bool monitor, hipStream_t stream) {
+    LBM_BATCH_SWITCH(launch_batch_step_s, rates_one, b, c, step, monitor, stream)
+}
+
+hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+                                   int step0, int nsteps, hipStream_t stream) {
+    LBM_BATCH_SWITCH(launch_batch_persistent_s, rates_one, b, c, step0, nsteps, stream)
+}
+
+hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks) {
+    LBM_BATCH_SWITCH(batch_persistent_capacity_s, rates_one, c, blocks)
+}
+
+#undef LBM_BATCH_SWITCH
+
+}  // namespace lbm

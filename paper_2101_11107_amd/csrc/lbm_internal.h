@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace lbm {
 
@@ -162,5 +163,20 @@ hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs&
                                    int step0, int nsteps, hipStream_t stream);
 // Work-groups of the persistent kernel that fit on the device at once.
 hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks);
+// One definition per storage type, each in its own translation unit; the
+// functions above dispatch to them.
+#define LBM_BATCH_DECL(K)                                                                                  \
+    hipError_t launch_batch_step_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,   \
+                                   int step, bool monitor, hipStream_t stream, std::integral_constant<int, K>); \
+    hipError_t launch_batch_persistent_s(int storage, bool rates_one, const BatchArgs& b,                  \
+                                         const BatchConfig& c, int step0, int nsteps, hipStream_t stream,   \
+                                         std::integral_constant<int, K>);                                   \
+    hipError_t batch_persistent_capacity_s(int storage, bool rates_one, const BatchConfig& c, int* blocks,  \
+                                           std::integral_constant<int, K>);
+LBM_BATCH_DECL(0)
+LBM_BATCH_DECL(1)
+LBM_BATCH_DECL(2)
+LBM_BATCH_DECL(3)
+#undef LBM_BATCH_DECL
 
 }  // namespace lbm
