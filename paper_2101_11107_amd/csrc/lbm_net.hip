@@ -305,16 +305,30 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
 // per wave) and writes one partial per work-group.  Per brick the input halo
 // goes to LDS channel-major ([ci][halo voxel]) and the output gradient
 // transposed ([co][brick voxel]), so an A fragment (4 voxels of one channel)
-// is one 8-byte read and a B fragment 4 consecutive 2-byte reads.
+// is one 8-byte read and a B fragment 4 consecutive 2-byte reads.  The global
+// loads of the next brick are issued into registers before the MFMA loop of
+// the current one, so their latency hides behind it (a work-group handles
+// many bricks in turn and only a few work-groups share a CU).
 constexpr int WG_TPW = 7;   // N-tiles per wave
+
+template <int PIECE>
+struct HaloPiece {
+    uint2 v;
+};
+template <>
+struct HaloPiece<16> {
+    uint4 v;
+};
 
 template <int CIN, int MT>
 __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts) {
     constexpr int PIECE = CIN * 2 >= 16 ? 16 : CIN * 2;
     constexpr int PPV = CIN * 2 / PIECE;
     constexpr int NHALO = HZ * HY * HX;
-    constexpr int NB = BX * BY * BZ;   // voxels per brick (256)
+    constexpr int NB = BX * BY * BZ;   // voxels per brick (256, one per thread)
     constexpr int N = 27 * CIN;
+    constexpr int HITER = (NHALO * PPV + 255) / 256;   // halo pieces per thread
+    constexpr int GQ = 4 * MT;                           // 4-channel gradient pieces per voxel, at most
     __shared__ __attribute__((aligned(16))) uint16_t halo[CIN * NHALO];
     __shared__ __attribute__((aligned(16))) uint16_t gy[MT * 16 * NB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -322,6 +336,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
     const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
     const int64_t nbricks = (int64_t)a.n * tx * ty * tz;
     const int64_t V = (int64_t)a.d * a.h * a.w;
+    const int gq = a.cout >> 2;
     // rows of the output gradient beyond cout stay zero
     for (int k = threadIdx.x; k < MT * 16 * NB; k += 256) gy[k] = 0;
     // this wave's N-tiles: column n -> (tap, ci)
@@ -339,7 +354,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int t = 0; t < WG_TPW; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int64_t br = blockIdx.x; br < nbricks; br += nparts) {
+
+    // Global loads of brick br into registers: halo pieces idx = tid + 256 i
+    // (voxel idx / PPV, piece idx % PPV; zeros outside the grid) and the
+    // gradient of brick voxel tid (cout / 4 pieces of 4 channels).
+    HaloPiece<PIECE> hreg[HITER];
+    uint2 greg[GQ];
+    auto fetch = [&](int64_t br) {
         int64_t b = br;
         const int bx = (int)(b % tx);
         b /= tx;
@@ -349,40 +370,62 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
         const int s = (int)(b / tz);
         const int xs = bx * BX - 1, ys = by * BY - 1, zs = bz * BZ - 1;
         const int64_t sbase = (int64_t)s * V;
-        __syncthreads();   // the previous brick's fragments have been read
-        for (int idx = threadIdx.x; idx < NHALO * PPV; idx += 256) {
+#pragma unroll
+        for (int i = 0; i < HITER; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
             const int vox = idx / PPV, p = idx - vox * PPV;
             const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
             const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
-            const bool in = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
+            const bool in = idx < NHALO * PPV && xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
             const uint16_t* src =
                 a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + p * (PIECE / 2);
-            uint16_t v[PIECE / 2];
-            if constexpr (PIECE == 16) {
-                const uint4 w4 = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
-                const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
+            if constexpr (PIECE == 16) hreg[i].v = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+            else hreg[i].v = in ? *(const uint2*)src : uint2{0u, 0u};
+        }
+        const int v = threadIdx.x;
+        const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
+        const int64_t g = sbase + ((int64_t)(zs + 1 + vz) * a.h + (ys + 1 + vy)) * a.w + (xs + 1 + vx);
+        const uint2* gsrc = (const uint2*)(a.dy + g * a.ldy);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    v[2 * e] = (uint16_t)(ww[e] & 0xffffu);
-                    v[2 * e + 1] = (uint16_t)(ww[e] >> 16);
-                }
+        for (int k = 0; k < GQ; ++k) greg[k] = k < gq ? gsrc[k] : uint2{0u, 0u};
+    };
+    // Registers -> LDS, with the layouts the fragments read.
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < HITER; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            if (idx >= NHALO * PPV) continue;
+            const int vox = idx / PPV, p = idx - vox * PPV;
+            uint32_t ww[PIECE / 4];
+            if constexpr (PIECE == 16) {
+                ww[0] = hreg[i].v.x, ww[1] = hreg[i].v.y, ww[2] = hreg[i].v.z, ww[3] = hreg[i].v.w;
             } else {
-                const uint2 w2 = in ? *(const uint2*)src : uint2{0u, 0u};
-                v[0] = (uint16_t)(w2.x & 0xffffu);
-                v[1] = (uint16_t)(w2.x >> 16);
-                v[2] = (uint16_t)(w2.y & 0xffffu);
-                v[3] = (uint16_t)(w2.y >> 16);
+                ww[0] = hreg[i].v.x, ww[1] = hreg[i].v.y;
             }
 #pragma unroll
-            for (int e = 0; e < PIECE / 2; ++e) halo[(p * (PIECE / 2) + e) * NHALO + vox] = v[e];
+            for (int e = 0; e < PIECE / 4; ++e) {
+                halo[(p * (PIECE / 2) + 2 * e) * NHALO + vox] = (uint16_t)(ww[e] & 0xffffu);
+                halo[(p * (PIECE / 2) + 2 * e + 1) * NHALO + vox] = (uint16_t)(ww[e] >> 16);
+            }
         }
-        for (int idx = threadIdx.x; idx < NB * a.cout; idx += 256) {
-            const int v = idx / a.cout, co = idx - v * a.cout;
-            const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
-            const int64_t g = sbase + ((int64_t)(zs + 1 + vz) * a.h + (ys + 1 + vy)) * a.w + (xs + 1 + vx);
-            gy[co * NB + v] = a.dy[g * a.ldy + co];
+        const int v = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < GQ; ++k) {
+            if (k >= gq) continue;
+            gy[(4 * k + 0) * NB + v] = (uint16_t)(greg[k].x & 0xffffu);
+            gy[(4 * k + 1) * NB + v] = (uint16_t)(greg[k].x >> 16);
+            gy[(4 * k + 2) * NB + v] = (uint16_t)(greg[k].y & 0xffffu);
+            gy[(4 * k + 3) * NB + v] = (uint16_t)(greg[k].y >> 16);
         }
+    };
+
+    int64_t br = blockIdx.x;
+    if (br < nbricks) fetch(br);
+    for (; br < nbricks; br += nparts) {
+        __syncthreads();   // the previous brick's fragments have been read
+        stage();
         __syncthreads();
+        if (br + nparts < nbricks) fetch(br + nparts);
 #pragma unroll 2
         for (int k0 = 0; k0 < NB; k0 += 16) {
             const int v0 = k0 + 4 * q;   // 4 voxels of one x row of the brick
@@ -414,6 +457,149 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
 #pragma unroll
             for (int j = 0; j < 4; ++j) part[(mt * 16 + 4 * q + j) * a.npad + n] = acc[mt][t][j];
         }
+}
+
+// --- weight gradient, one output tile of 16 channels, waves split the brick -------
+// For cout <= 16 and cin a multiple of 16.  Work-group (p, yb) covers input
+// channels 16 yb .. 16 yb + 15 and all 27 taps (27 N-tiles) over the bricks
+// p, p + P, ...; wave w takes the z-slice w of every brick (64 voxels, four
+// K-steps of 16).  For one (dz, dy) the B fragments of dx = 0, 1, 2 are
+// windows of six consecutive halo values starting at an even index, so
+// three aligned 4-byte LDS reads give all three (dx = 1 by a 16-bit funnel
+// shift): 27 MFMAs per K-step for 28 LDS reads, against 7 MFMAs for 29 reads
+// when the waves split the taps.  The four waves' sums are added in LDS in
+// a fixed order (wave 3, 2, 1, 0) before the partial is written.
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts) {
+    constexpr int NHALO = HZ * HY * HX;
+    constexpr int NB = BX * BY * BZ;                 // voxels per brick (256, one per thread)
+    constexpr int HITER = (NHALO * 2 + 255) / 256;   // 16-byte halo pieces per thread (8 channels each)
+    constexpr int LDS_HALFS = 16 * NHALO + 16 * NB;
+    static_assert(BZ == 4 && BX == 16 && BY == 4, "one z-slice per wave, four K-steps of 16 per slice");
+    static_assert(27 * 4 * 64 * 4 <= LDS_HALFS * 2, "the wave reduction fits in the staging space");
+    __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_HALFS];
+    uint16_t* halo = lds;                 // [16 channels][NHALO]
+    uint16_t* gy = lds + 16 * NHALO;      // [16 output channels][NB]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
+    const int64_t nbricks = (int64_t)a.n * tx * ty * tz;
+    const int64_t V = (int64_t)a.d * a.h * a.w;
+    const int gq = a.cout >> 2;
+    const int c0 = 16 * (int)blockIdx.y;   // first input channel of this work-group
+    for (int k = threadIdx.x; k < 16 * NB; k += 256) gy[k] = 0;   // rows co >= cout stay zero
+    v4f acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    uint4 hreg[HITER];
+    uint2 greg[4];
+    auto fetch = [&](int64_t br) {
+        int64_t b = br;
+        const int bx = (int)(b % tx);
+        b /= tx;
+        const int by = (int)(b % ty);
+        b /= ty;
+        const int bz = (int)(b % tz);
+        const int s = (int)(b / tz);
+        const int xs = bx * BX - 1, ys = by * BY - 1, zs = bz * BZ - 1;
+        const int64_t sbase = (int64_t)s * V;
+#pragma unroll
+        for (int i = 0; i < HITER; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            const int vox = idx >> 1, p = idx & 1;
+            const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+            const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
+            const bool in = idx < NHALO * 2 && xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
+            const uint16_t* src = a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + c0 + 8 * p;
+            hreg[i] = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+        }
+        const int v = threadIdx.x;
+        const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
+        const int64_t g = sbase + ((int64_t)(zs + 1 + vz) * a.h + (ys + 1 + vy)) * a.w + (xs + 1 + vx);
+        const uint2* gsrc = (const uint2*)(a.dy + g * a.ldy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) greg[k] = k < gq ? gsrc[k] : uint2{0u, 0u};
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < HITER; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            if (idx >= NHALO * 2) continue;
+            const int vox = idx >> 1, p = idx & 1;
+            const uint32_t ww[4] = {hreg[i].x, hreg[i].y, hreg[i].z, hreg[i].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                halo[(8 * p + 2 * e) * NHALO + vox] = (uint16_t)(ww[e] & 0xffffu);
+                halo[(8 * p + 2 * e + 1) * NHALO + vox] = (uint16_t)(ww[e] >> 16);
+            }
+        }
+        const int v = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= gq) continue;
+            gy[(4 * k + 0) * NB + v] = (uint16_t)(greg[k].x & 0xffffu);
+            gy[(4 * k + 1) * NB + v] = (uint16_t)(greg[k].x >> 16);
+            gy[(4 * k + 2) * NB + v] = (uint16_t)(greg[k].y & 0xffffu);
+            gy[(4 * k + 3) * NB + v] = (uint16_t)(greg[k].y >> 16);
+        }
+    };
+
+    // lane (q, r16): input channel c0 + r16, voxels x = 4q .. 4q + 3 of each
+    // brick row (an even halo index, so 4-byte aligned)
+    const uint16_t* hl = halo + r16 * NHALO + wave * (HY * HX) + 4 * q;
+    const uint16_t* gl = gy + r16 * NB + wave * (BX * BY) + 4 * q;
+    int64_t br = blockIdx.x;
+    if (br < nbricks) fetch(br);
+    for (; br < nbricks; br += nparts) {
+        __syncthreads();   // the previous brick's fragments have been read
+        stage();
+        __syncthreads();
+        if (br + nparts < nbricks) fetch(br + nparts);
+#pragma unroll
+        for (int s = 0; s < BY; ++s) {   // K-step: voxels (4q .. 4q + 3, y = s, z = wave)
+            const v4s am = *(const v4s*)(gl + s * BX);
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const uint32_t* rw = (const uint32_t*)(hl + (dz * HY + s + dy) * HX);
+                    const uint32_t d0 = rw[0], d1 = rw[1], d2 = rw[2];
+                    const uint32_t m0 = __builtin_amdgcn_alignbit(d1, d0, 16);
+                    const uint32_t m1 = __builtin_amdgcn_alignbit(d2, d1, 16);
+                    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+                    const int t0 = dz * 9 + dy * 3;
+                    acc[t0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        am, __builtin_bit_cast(v4s, u2{d0, d1}), acc[t0], 0, 0, 0);
+                    acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        am, __builtin_bit_cast(v4s, u2{m0, m1}), acc[t0 + 1], 0, 0, 0);
+                    acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        am, __builtin_bit_cast(v4s, u2{d1, d2}), acc[t0 + 2], 0, 0, 0);
+                }
+        }
+    }
+    // sum over the waves: red[(t * 4 + j) * 64 + lane], wave 3 first
+    float* red = (float*)lds;
+    for (int w = 3; w >= 0; --w) {
+        __syncthreads();
+        if (wave != w) continue;
+#pragma unroll
+        for (int t = 0; t < 27; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float* r = red + (t * 4 + j) * 64 + lane;
+                acc[t][j] = w == 3 ? acc[t][j] : *r + acc[t][j];
+                if (w > 0) *r = acc[t][j];
+            }
+    }
+    if (wave != 0) return;
+    float* part = a.part + (int64_t)blockIdx.x * a.mpad * a.npad;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int n = t * CIN + c0 + r16;   // column of (tap t, input channel c0 + r16)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[(4 * q + j) * a.npad + n] = acc[t][j];
+    }
 }
 
 // dW[co][n] = sum over chunks, only co < cout_param written.  A work-group
@@ -823,12 +1009,17 @@ hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, f
     // brick kernel: same tiling and alignment conditions as the forward one;
     // at most nchunks partials (the size the caller's partial buffer holds)
     const bool bricks = a.d % BZ == 0 && a.h % BY == 0 && a.w % BX == 0 && a.npad == (27 * a.cin + 15) / 16 * 16 &&
-                        a.cout <= 16 * mt;
+                        a.cout <= 16 * mt && a.cout % 4 == 0 && a.ldy % 4 == 0 && ((uintptr_t)a.dy & 7) == 0;
     const int64_t nbricks = (int64_t)a.n * (a.d / BZ) * (a.h / BY) * (a.w / BX);
     const int nparts = (int)(nbricks < nchunks ? nbricks : nchunks);
     hipError_t e;
     int nred = nparts;   // partials the reduction sums
-    if (bricks && a.cin == 16 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
+    if (bricks && mt == 1 && a.cin % 16 == 0 && a.cin <= 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
+        const dim3 grid(nparts, a.cin / 16);
+        if (a.cin == 16) hipLaunchKernelGGL(k_conv_wgrad_k16<16>, grid, dim3(256), 0, st, a, nparts);
+        else hipLaunchKernelGGL(k_conv_wgrad_k16<32>, grid, dim3(256), 0, st, a, nparts);
+        e = hipGetLastError();
+    } else if (bricks && a.cin == 16 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
         e = wgrad_lds<16>(a, mt, nparts, st);
     } else if (bricks && a.cin == 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
         e = wgrad_lds<32>(a, mt, nparts, st);

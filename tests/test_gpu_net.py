@@ -44,6 +44,12 @@ LAYER_CASES = [
     (32, 16, 0, (1, 4, 8, 16)),
     (32, 32, 1, (2, 4, 4, 32)),
     (16, 4, 1, (1, 4, 4, 48)),
+    # more bricks than weight-gradient partials (at most 512): each work-group
+    # of the brick kernel steps through several bricks
+    (16, 16, 1, (1, 32, 64, 128)),
+    (4, 16, 1, (1, 32, 64, 128)),
+    (16, 32, 0, (1, 32, 64, 128)),
+    (32, 16, 1, (1, 32, 64, 128)),
 ]
 
 
