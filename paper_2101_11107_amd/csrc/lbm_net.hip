@@ -616,7 +616,15 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
         const int co = e / N, n = e - co * N;
         const float* p = part + (int64_t)co * npad + n;
         const int64_t stride = (int64_t)mpad * npad;
-        for (int c = grp; c < nchunks; c += 8) acc += p[c * stride];
+        // eight partials per round, loaded before they are added (ascending order)
+        for (int c0 = grp; c0 < nchunks; c0 += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = c0 + 8 * u < nchunks ? p[(c0 + 8 * u) * stride] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (c0 + 8 * u < nchunks) acc += v[u];
+        }
     }
     s[grp][lane] = acc;
     __syncthreads();
@@ -680,14 +688,34 @@ __global__ __launch_bounds__(256) void k_grad_relu_cast(float* __restrict__ g, i
     const int64_t e0 = (int64_t)blockIdx.x * per;
     const int64_t e1 = e0 + per < E ? e0 + per : E;
     float acc = 0.0f;
-    for (int64_t idx = e0 + threadIdx.x; idx < e1; idx += 256) {
-        const int64_t v = idx / c;
-        const int ch = (int)(idx - v * c);
-        float val = g[v * ldg + offg + ch];
-        if (act && !(bf2f(act[v * lda + offa + ch]) > 0.0f)) val = 0.0f;
-        g[v * ldg + offg + ch] = val;
-        out[idx] = f2bf(val);
-        acc += val;
+    // c is a power of two dividing 256 and e0 a multiple of 256: the channel
+    // of every element this thread visits is threadIdx.x mod c
+    const int ch = threadIdx.x & (c - 1);
+    const int csh = __builtin_ctz((unsigned)c);
+    // four elements per round: their loads are issued before the in-place
+    // stores (which the compiler may not move loads across); the sum keeps
+    // ascending element order
+    constexpr int U = 4;
+    for (int64_t i0 = e0 + threadIdx.x; i0 < e1; i0 += 256 * U) {
+        float val[U];
+        bool keep[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = i0 + 256 * u;
+            const int64_t v = idx >> csh;
+            val[u] = idx < e1 ? g[v * ldg + offg + ch] : 0.0f;
+            keep[u] = !act || (idx < e1 && bf2f(act[v * lda + offa + ch]) > 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = i0 + 256 * u;
+            if (idx >= e1) break;
+            const int64_t v = idx >> csh;
+            const float x = keep[u] ? val[u] : 0.0f;
+            g[v * ldg + offg + ch] = x;
+            out[idx] = f2bf(x);
+            acc += x;
+        }
     }
     s[threadIdx.x] = acc;
     __syncthreads();
