@@ -208,20 +208,40 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvArgs a) {
             }
         }
     }
+    // a lane holds channels 4q .. 4q + 3 of one voxel: one 16-byte (FP32) or
+    // 8-byte (BF16) store when they are aligned and all valid or all absent
+    const bool vec = a.cout % 4 == 0 && a.ldy % 4 == 0 && a.cyo % 4 == 0 &&
+                     ((uintptr_t)a.y & (F32OUT ? 15 : 7)) == 0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int64_t vox = sbase + ((int64_t)(zs + 1 + wave) * a.h + (ys + 1 + t)) * a.w + (xs + 1 + r16);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
+            const int co0 = mt * 16 + 4 * q;
+            float val[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int co = mt * 16 + 4 * q + j;
-                if (co >= a.cout) continue;
-                float val = acc[mt][t][j] + (a.bias ? a.bias[co] : 0.0f);
-                if (a.relu) val = val > 0.0f ? val : 0.0f;
-                const int64_t idx = vox * a.ldy + a.cyo + co;
-                if (F32OUT) ((float*)a.y)[idx] = val;
-                else ((uint16_t*)a.y)[idx] = f2bf(val);
+                const int co = co0 + j;
+                val[j] = acc[mt][t][j] + (a.bias && co < a.cout ? a.bias[co] : 0.0f);
+                if (a.relu) val[j] = val[j] > 0.0f ? val[j] : 0.0f;
+            }
+            const int64_t idx0 = vox * a.ldy + a.cyo + co0;
+            if (vec) {
+                if (co0 >= a.cout) continue;
+                if (F32OUT) {
+                    *(float4*)((float*)a.y + idx0) = float4{val[0], val[1], val[2], val[3]};
+                } else {
+                    const uint32_t lo = (uint32_t)f2bf(val[0]) | ((uint32_t)f2bf(val[1]) << 16);
+                    const uint32_t hi = (uint32_t)f2bf(val[2]) | ((uint32_t)f2bf(val[3]) << 16);
+                    *(uint2*)((uint16_t*)a.y + idx0) = uint2{lo, hi};
+                }
+                continue;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (co0 + j >= a.cout) continue;
+                if (F32OUT) ((float*)a.y)[idx0 + j] = val[j];
+                else ((uint16_t*)a.y)[idx0 + j] = f2bf(val[j]);
             }
         }
     }
