@@ -835,57 +835,68 @@ __global__ void k_avgpool_fwd(const uint16_t* __restrict__ x, int ld, int off, i
 // Adjoint of the pooling: g[child][off + ch] += gy[parent][ch] / 8 (FP32).
 __global__ void k_avgpool_bwd_add(const float* __restrict__ gy, int c, int n, int d, int h, int w, float* __restrict__ g,
                                   int ld, int off) {
-    const int64_t total = (int64_t)n * d * h * w * c;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // one thread per fine voxel and four channels; 32-bit indices
+    const uint32_t c4 = (uint32_t)c >> 2;
+    const uint32_t total = (uint32_t)n * d * h * w * c4;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    int64_t r = idx;
-    const int ch = (int)(r % c); r /= c;
-    const int x = (int)(r % w); r /= w;
-    const int y = (int)(r % h); r /= h;
-    const int z = (int)(r % d);
-    const int s = (int)(r / d);
-    const int64_t p = (((int64_t)s * (d / 2) + z / 2) * (h / 2) + y / 2) * (w / 2) + x / 2;
-    const int64_t v = ((int64_t)s * d + z) * h * w + (int64_t)y * w + x;
-    g[v * ld + off + ch] += 0.125f * gy[p * c + ch];
+    uint32_t r = idx;
+    const uint32_t q4 = r % c4; r /= c4;
+    const uint32_t x = r % (uint32_t)w; r /= (uint32_t)w;
+    const uint32_t y = r % (uint32_t)h; r /= (uint32_t)h;
+    const uint32_t z = r % (uint32_t)d;
+    const uint32_t s = r / (uint32_t)d;
+    const uint32_t p = ((s * (d / 2) + z / 2) * (h / 2) + y / 2) * (w / 2) + x / 2;
+    const uint32_t v = ((s * d + z) * h + y) * w + x;
+    const float4 t = *(const float4*)(gy + (int64_t)p * c + 4 * q4);
+    float4* dst = (float4*)(g + (int64_t)v * ld + off + 4 * q4);
+    float4 o = *dst;
+    o.x += 0.125f * t.x, o.y += 0.125f * t.y, o.z += 0.125f * t.z, o.w += 0.125f * t.w;
+    *dst = o;
 }
 
 // Nearest 2x upsampling of BF16 [V][c] (coarse dims d, h, w) into packed
 // [8V][c]; c a multiple of 8, copied in 16-byte pieces.
 __global__ void k_upsample_fwd(const uint16_t* __restrict__ x, int c, int n, int d, int h, int w,
                                uint16_t* __restrict__ y) {
-    const int D = 2 * d, H = 2 * h, W = 2 * w;
-    const int c8 = c / 8;
-    const int64_t total = (int64_t)n * D * H * W * c8;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t D = 2 * d, H = 2 * h, W = 2 * w;
+    const uint32_t c8 = (uint32_t)c / 8;
+    const uint32_t total = (uint32_t)n * D * H * W * c8;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    int64_t r = idx;
-    const int part = (int)(r % c8); r /= c8;
-    const int X = (int)(r % W); r /= W;
-    const int Y = (int)(r % H); r /= H;
-    const int Z = (int)(r % D);
-    const int s = (int)(r / D);
-    const int64_t p = (((int64_t)s * d + Z / 2) * h + Y / 2) * w + X / 2;
-    ((uint4*)y)[idx] = ((const uint4*)x)[p * c8 + part];
+    uint32_t r = idx;
+    const uint32_t part = r % c8; r /= c8;
+    const uint32_t X = r % W; r /= W;
+    const uint32_t Y = r % H; r /= H;
+    const uint32_t Z = r % D;
+    const uint32_t s = r / D;
+    const uint32_t p = ((s * d + Z / 2) * h + Y / 2) * w + X / 2;
+    ((uint4*)y)[idx] = ((const uint4*)x)[(int64_t)p * c8 + part];
 }
 
 // Adjoint of the upsampling: g[parent][ch] = sum of the 8 children (FP32, packed).
 __global__ void k_upsample_bwd(const float* __restrict__ gy, int c, int n, int d, int h, int w, float* __restrict__ g) {
-    const int64_t total = (int64_t)n * d * h * w * c;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // one thread per coarse voxel and four channels; 32-bit indices (the host
+    // checks the sizes)
+    const uint32_t c4 = (uint32_t)c >> 2;
+    const uint32_t total = (uint32_t)n * d * h * w * c4;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    int64_t r = idx;
-    const int ch = (int)(r % c); r /= c;
-    const int x = (int)(r % w); r /= w;
-    const int y = (int)(r % h); r /= h;
-    const int z = (int)(r % d);
-    const int s = (int)(r / d);
-    const int H = 2 * h, W = 2 * w;
-    float acc = 0.0f;
+    uint32_t r = idx;
+    const uint32_t q4 = r % c4; r /= c4;
+    const uint32_t x = r % (uint32_t)w; r /= (uint32_t)w;
+    const uint32_t y = r % (uint32_t)h; r /= (uint32_t)h;
+    const uint32_t z = r % (uint32_t)d;
+    const uint32_t s = r / (uint32_t)d;
+    const uint32_t H = 2 * h, W = 2 * w;
+    float4 acc = float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int64_t v = (((int64_t)s * 2 * d + 2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
-        acc += gy[v * c + ch];
+        const uint32_t v = ((s * 2 * d + 2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+        const float4 t = *(const float4*)(gy + (int64_t)v * c + 4 * q4);
+        acc.x += t.x, acc.y += t.y, acc.z += t.z, acc.w += t.w;
     }
-    g[idx] = acc;
+    *(float4*)(g + (int64_t)idx * 4) = acc;
 }
 
 // Fixed trilinear upsampling of channels 0..2 of the FP32 coarse input (row 4):
@@ -1195,22 +1206,29 @@ hipError_t avgpool_fwd(const uint16_t* x, int ld, int off, int c, int n, int d, 
 
 hipError_t avgpool_bwd_add(const float* gy, int c, int n, int d, int h, int w, float* g, int ld, int off,
                            hipStream_t st) {
-    const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(k_avgpool_bwd_add, dim3(blocks_for(total, 256)), dim3(256), 0, st, gy, c, n, d, h, w, g, ld,
-                       off);
+    // four channels per thread, 16-byte aligned rows, 32-bit voxel indices
+    const int64_t vox = (int64_t)n * d * h * w;
+    if (c % 4 != 0 || ld % 4 != 0 || off % 4 != 0 || ((uintptr_t)g & 15) || ((uintptr_t)gy & 15) ||
+        vox * (ld > c ? ld : c) >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_avgpool_bwd_add, dim3(blocks_for(vox * (c / 4), 256)), dim3(256), 0, st, gy, c, n, d, h, w, g,
+                       ld, off);
     return hipGetLastError();
 }
 
 hipError_t upsample_fwd(const uint16_t* x, int c, int n, int d, int h, int w, uint16_t* y, hipStream_t st) {
-    if (c % 8 != 0) return hipErrorInvalidValue;
     const int64_t total = (int64_t)n * 8 * d * h * w * (c / 8);
+    if (c % 8 != 0 || total * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_upsample_fwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, x, c, n, d, h, w, y);
     return hipGetLastError();
 }
 
 hipError_t upsample_bwd(const float* gy, int c, int n, int d, int h, int w, float* g, hipStream_t st) {
-    const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(k_upsample_bwd, dim3(blocks_for(total, 256)), dim3(256), 0, st, gy, c, n, d, h, w, g);
+    // four channels per thread, 32-bit indices over the fine grid
+    const int64_t vox = (int64_t)n * d * h * w;
+    if (c % 4 != 0 || ((uintptr_t)g & 15) || ((uintptr_t)gy & 15) || vox * 8 * c >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_upsample_bwd, dim3(blocks_for(vox * (c / 4), 256)), dim3(256), 0, st, gy, c, n, d, h, w, g);
     return hipGetLastError();
 }
 
