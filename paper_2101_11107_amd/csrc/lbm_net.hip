@@ -565,10 +565,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
         }
     };
 
-    // lane (q, r16): input channel c0 + r16, voxels x = 4q .. 4q + 3 of each
-    // brick row (an even halo index, so 4-byte aligned)
-    const uint16_t* hl = halo + r16 * NHALO + wave * (HY * HX) + 4 * q;
-    const uint16_t* gl = gy + r16 * NB + wave * (BX * BY) + 4 * q;
+    // v_mfma_f32_16x16x32_bf16, two K-steps of 32 voxels per slice: lane
+    // (q, r16) takes input channel c0 + r16 and the 8 voxels x = 8 (q & 1) ..
+    // + 7 of row y = 2 m + (q >> 1) (an even halo index, so 4-byte aligned)
+    const int xq = 8 * (q & 1), yq = q >> 1;
+    const uint16_t* hl = halo + r16 * NHALO + (wave * HY + yq) * HX + xq;
+    const uint16_t* gl = gy + r16 * NB + wave * (BX * BY) + yq * BX + xq;
     int64_t br = blockIdx.x;
     if (br < nbricks) fetch(br);
     for (; br < nbricks; br += nparts) {
@@ -576,25 +578,28 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
         stage();
         __syncthreads();
         if (br + nparts < nbricks) fetch(br + nparts);
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int s = 0; s < BY; ++s) {   // K-step: voxels (4q .. 4q + 3, y = s, z = wave)
-            const v4s am = *(const v4s*)(gl + s * BX);
+        for (int m = 0; m < BY / 2; ++m) {   // K-step: rows 2m, 2m + 1 of slice z = wave
+            const v8b am = *(const v8b*)(gl + 2 * m * BX);
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
-                    const uint32_t* rw = (const uint32_t*)(hl + (dz * HY + s + dy) * HX);
-                    const uint32_t d0 = rw[0], d1 = rw[1], d2 = rw[2];
-                    const uint32_t m0 = __builtin_amdgcn_alignbit(d1, d0, 16);
-                    const uint32_t m1 = __builtin_amdgcn_alignbit(d2, d1, 16);
-                    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+                    // ten halo values x0 .. x0 + 9 of the row give the windows of dx = 0, 1, 2
+                    const uint32_t* rw = (const uint32_t*)(hl + (dz * HY + 2 * m + dy) * HX);
+                    const uint32_t e0 = rw[0], e1 = rw[1], e2 = rw[2], e3 = rw[3], e4 = rw[4];
+                    const uint32_t m0 = __builtin_amdgcn_alignbit(e1, e0, 16);
+                    const uint32_t m1 = __builtin_amdgcn_alignbit(e2, e1, 16);
+                    const uint32_t m2 = __builtin_amdgcn_alignbit(e3, e2, 16);
+                    const uint32_t m3 = __builtin_amdgcn_alignbit(e4, e3, 16);
                     const int t0 = dz * 9 + dy * 3;
-                    acc[t0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                        am, __builtin_bit_cast(v4s, u2{d0, d1}), acc[t0], 0, 0, 0);
-                    acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                        am, __builtin_bit_cast(v4s, u2{m0, m1}), acc[t0 + 1], 0, 0, 0);
-                    acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                        am, __builtin_bit_cast(v4s, u2{d1, d2}), acc[t0 + 2], 0, 0, 0);
+                    acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        am, __builtin_bit_cast(v8b, u4{e0, e1, e2, e3}), acc[t0], 0, 0, 0);
+                    acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        am, __builtin_bit_cast(v8b, u4{m0, m1, m2, m3}), acc[t0 + 1], 0, 0, 0);
+                    acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        am, __builtin_bit_cast(v8b, u4{e1, e2, e3, e4}), acc[t0 + 2], 0, 0, 0);
                 }
         }
     }
