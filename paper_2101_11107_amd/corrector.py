@@ -119,21 +119,27 @@ def train(pairs: list, cfg: TrainConfig, params: np.ndarray | None = None, log=p
     xin = torch.empty((cfg.batch, c, c, c, 4), dtype=torch.float32, device=dev)
     tgt = torch.empty((cfg.batch, 2 * c, 2 * c, 2 * c, 3), dtype=torch.float32, device=dev)
     tmask = torch.empty((cfg.batch, 2 * c, 2 * c, 2 * c), dtype=torch.uint8, device=dev)
-    origins = torch.empty((cfg.batch, 3), dtype=torch.int32, device=dev)
     fluid = [np.argwhere(p.coarse.mask.cpu().numpy()) for p in pairs]
     shapes = [tuple(p.coarse.mask.shape) for p in pairs]
     res = TrainResult(params=None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # every crop of the run drawn up front, in the order one iteration at a
+    # time would draw them, and copied to the device once: the loop then
+    # makes no synchronizing host-to-device copy and the host does not wait
+    # for the GPU between steps
+    picks_all = np.empty((cfg.iters, cfg.batch), np.int64)
+    org_all = np.empty((cfg.iters, cfg.batch, 3), np.int32)
+    for it in range(cfg.iters):
+        picks_all[it] = rng.integers(0, len(pairs), cfg.batch)
+        org_all[it] = [_crop_origin(rng, fluid[k], shapes[k], c) for k in picks_all[it]]
+    origins = torch.from_numpy(org_all).to(dev)
     st = model.stream.cuda_stream
     for it in range(cfg.iters):
-        picks = rng.integers(0, len(pairs), cfg.batch)
-        org = np.array([_crop_origin(rng, fluid[k], shapes[k], c) for k in picks], np.int32)
-        origins.copy_(torch.from_numpy(org))
         model._in()
-        for s, k in enumerate(picks):
+        for s, k in enumerate(picks_all[it]):
             p = pairs[k]
-            nn.lbmnet_crop(p.coarse.u, p.coarse.mask, p.fine.u, p.fine.mask, origins[s: s + 1], c, c, c,
+            nn.lbmnet_crop(p.coarse.u, p.coarse.mask, p.fine.u, p.fine.mask, origins[it, s: s + 1], c, c, c,
                            cfg.margin, xin[s: s + 1], tgt[s: s + 1], tmask[s: s + 1], st)
         want = (it % cfg.log_every == 0) or it == cfg.iters - 1
         loss = model.loss_grad(xin, tgt, tmask, want_loss=want)

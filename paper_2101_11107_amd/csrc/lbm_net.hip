@@ -1027,30 +1027,33 @@ __global__ void k_crop(const float* __restrict__ uc, const uint8_t* __restrict__
                        const float* __restrict__ uf, const uint8_t* __restrict__ mf, const int* __restrict__ origin,
                        int n, int d, int h, int w, int margin, float* __restrict__ xin, float* __restrict__ tgt,
                        uint8_t* __restrict__ tmask) {
-    const int64_t Vc = (int64_t)d * h * w, Vf = 8 * Vc;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < n * Vc) {
-        const int s = (int)(idx / Vc);
-        int64_t r = idx - s * Vc;
-        const int x = (int)(r % w), y = (int)((r / w) % h), z = (int)(r / ((int64_t)w * h));
+    // 32-bit indices: the host checks that the fine crops and the source
+    // grids stay below 2^31 values
+    const uint32_t Vc = (uint32_t)d * h * w, Vf = 8 * Vc;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (uint32_t)n * Vc) {
+        const uint32_t s = idx / Vc;
+        const uint32_t r = idx - s * Vc;
+        const int x = (int)(r % (uint32_t)w), y = (int)((r / (uint32_t)w) % (uint32_t)h), z = (int)(r / ((uint32_t)w * h));
         const int Z = origin[3 * s] + z, Y = origin[3 * s + 1] + y, X = origin[3 * s + 2] + x;
         const bool in = Z >= 0 && Z < Dc && Y >= 0 && Y < Hc && X >= 0 && X < Wc;
-        const int64_t src = in ? ((int64_t)Z * Hc + Y) * Wc + X : 0;
-        for (int c = 0; c < 3; ++c) xin[idx * 4 + c] = in ? uc[src * 3 + c] : 0.0f;
-        xin[idx * 4 + 3] = in ? (float)mc[src] : 0.0f;
+        const uint32_t src = in ? ((uint32_t)Z * Hc + Y) * Wc + X : 0;
+        for (int c = 0; c < 3; ++c) xin[(int64_t)idx * 4 + c] = in ? uc[(int64_t)src * 3 + c] : 0.0f;
+        xin[(int64_t)idx * 4 + 3] = in ? (float)mc[src] : 0.0f;
     }
-    if (idx < n * Vf) {
-        const int s = (int)(idx / Vf);
-        int64_t r = idx - s * Vf;
-        const int W2 = 2 * w, H2 = 2 * h, D2 = 2 * d;
-        const int x = (int)(r % W2), y = (int)((r / W2) % H2), z = (int)(r / ((int64_t)W2 * H2));
+    if (idx < (uint32_t)n * Vf) {
+        const uint32_t s = idx / Vf;
+        const uint32_t r = idx - s * Vf;
+        const uint32_t W2 = 2 * w, H2 = 2 * h;
+        const int D2 = 2 * d;
+        const int x = (int)(r % W2), y = (int)((r / W2) % H2), z = (int)(r / (W2 * H2));
         const int Z = 2 * origin[3 * s] + z, Y = 2 * origin[3 * s + 1] + y, X = 2 * origin[3 * s + 2] + x;
         const int Df = 2 * Dc, Hf = 2 * Hc, Wf = 2 * Wc;
         const bool in = Z >= 0 && Z < Df && Y >= 0 && Y < Hf && X >= 0 && X < Wf;
-        const int64_t src = in ? ((int64_t)Z * Hf + Y) * Wf + X : 0;
-        for (int c = 0; c < 3; ++c) tgt[idx * 3 + c] = in ? uf[src * 3 + c] : 0.0f;
-        const bool inner = z >= margin && z < D2 - margin && y >= margin && y < H2 - margin && x >= margin &&
-                           x < W2 - margin;
+        const uint32_t src = in ? ((uint32_t)Z * Hf + Y) * Wf + X : 0;
+        for (int c = 0; c < 3; ++c) tgt[(int64_t)idx * 3 + c] = in ? uf[(int64_t)src * 3 + c] : 0.0f;
+        const bool inner = z >= margin && z < D2 - margin && y >= margin && y < (int)H2 - margin && x >= margin &&
+                           x < (int)W2 - margin;
         tmask[idx] = (in && inner && mf[src]) ? 1 : 0;
     }
 }
@@ -1268,6 +1271,7 @@ hipError_t crop(const float* uc, const uint8_t* mc, int Dc, int Hc, int Wc, cons
                 const int* origin, int n, int d, int h, int w, int margin, float* xin, float* tgt, uint8_t* tmask,
                 hipStream_t st) {
     const int64_t total = (int64_t)n * 8 * d * h * w;
+    if (total >= ((int64_t)1 << 31) || (int64_t)8 * Dc * Hc * Wc >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_crop, dim3(blocks_for(total, 256)), dim3(256), 0, st, uc, mc, Dc, Hc, Wc, uf, mf, origin, n,
                        d, h, w, margin, xin, tgt, tmask);
     return hipGetLastError();
