@@ -630,8 +630,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
 // dW[co][n] = sum over chunks, only co < cout_param written.  A work-group
 // covers 32 outputs; each of its 8 thread groups sums every 8th chunk in
 // ascending order, then the 8 group sums are added in order (deterministic).
+// Work-groups from wblocks on reduce the bias gradient of the same layer
+// instead (channel blockIdx.x - wblocks), saving a launch.
+__device__ __forceinline__ void bias_reduce_block(const float* __restrict__ part, int nparts, float* __restrict__ db,
+                                                  int co);
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int mpad, int npad,
-                                                      int cout_param, int N, float* __restrict__ dw) {
+                                                      int cout_param, int N, float* __restrict__ dw, int wblocks,
+                                                      const float* __restrict__ bpart, int bnparts,
+                                                      float* __restrict__ db) {
+    if ((int)blockIdx.x >= wblocks) {
+        bias_reduce_block(bpart, bnparts, db, (int)blockIdx.x - wblocks);
+        return;
+    }
     __shared__ float s[8][32];
     const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int e = blockIdx.x * 32 + lane;
@@ -662,10 +672,9 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
 
 // Bias gradient from the per-work-group channel sums of k_grad_relu_cast: one
 // work-group per channel, fixed-order tree (deterministic).
-__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ part, int nparts,
-                                                     float* __restrict__ db) {
+__device__ __forceinline__ void bias_reduce_block(const float* __restrict__ part, int nparts, float* __restrict__ db,
+                                                  int co) {
     __shared__ float s[256];
-    const int co = blockIdx.x;
     float acc = 0.0f;
     for (int b = threadIdx.x; b < nparts; b += 256) acc += part[b * 64 + co];
     s[threadIdx.x] = acc;
@@ -677,11 +686,15 @@ __global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ p
     if (threadIdx.x == 0) db[co] = s[0];
 }
 
+__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ part, int nparts,
+                                                     float* __restrict__ db) {
+    bias_reduce_block(part, nparts, db, blockIdx.x);
+}
+
 // Packed BF16 weights from FP32 masters w[co][tap][ci] (rows co >= cout_param zero):
 // forward wt[m][tap * cin + ci], input-gradient wd[ci][tap' * cout + co] = w[co][26 - tap'][ci].
-__global__ void k_prep_weights(const float* __restrict__ w, int cin, int cout_param, int cout, uint16_t* wt, int mpad,
-                               int kpad, uint16_t* wd, int mpad_d, int kpad_d) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prep_one(const float* __restrict__ w, int cin, int cout_param, int cout, uint16_t* wt,
+                                         int mpad, int kpad, uint16_t* wd, int mpad_d, int kpad_d, int idx) {
     if (idx < mpad * kpad) {
         const int m = idx / kpad, k = idx - m * kpad;
         float v = 0.0f;
@@ -697,6 +710,18 @@ __global__ void k_prep_weights(const float* __restrict__ w, int cin, int cout_pa
         }
         wd[idx] = f2bf(v);
     }
+}
+
+__global__ void k_prep_weights(const float* __restrict__ w, int cin, int cout_param, int cout, uint16_t* wt, int mpad,
+                               int kpad, uint16_t* wd, int mpad_d, int kpad_d) {
+    prep_one(w, cin, cout_param, cout, wt, mpad, kpad, wd, mpad_d, kpad_d, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Every layer of a network in one launch: row blockIdx.y packs layer y.
+__global__ void k_prep_weights_all(PrepJobs jobs) {
+    const PrepJob& p = jobs.j[blockIdx.y];
+    prep_one(p.w, p.cin, p.cout_param, p.cout, p.wt, p.mpad, p.kpad, p.wd, p.mpad_d, p.kpad_d,
+             blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // g (FP32, channels [off, off + c) of rows of length ld) times the ReLU mask of
@@ -1131,7 +1156,8 @@ hipError_t wgrad_lds(const WgradArgs& a, int mt, int nparts, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st) {
+hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st,
+                      const BiasJob* bias) {
     const int ntiles = a.npad / 16;
     // brick kernel: same tiling and alignment conditions as the forward one;
     // at most nchunks partials (the size the caller's partial buffer holds)
@@ -1162,8 +1188,24 @@ hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, f
     }
     if (e != hipSuccess) return e;
     const int N = 27 * a.cin;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout_param * N, 32)), dim3(256), 0, st, a.part,
-                       nred, a.mpad, a.npad, cout_param, N, dw);
+    const int wblocks = (int)blocks_for((int64_t)cout_param * N, 32);
+    const int bblocks = bias ? bias->cout_param : 0;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(wblocks + bblocks), dim3(256), 0, st, a.part, nred, a.mpad, a.npad,
+                       cout_param, N, dw, wblocks, bias ? bias->part : nullptr, bias ? bias->nparts : 0,
+                       bias ? bias->db : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t prep_weights_all(const PrepJobs& jobs, hipStream_t st) {
+    if (jobs.n < 1 || jobs.n > MAX_PREP_JOBS) return hipErrorInvalidValue;
+    int64_t n = 0;
+    for (int i = 0; i < jobs.n; ++i) {
+        const PrepJob& p = jobs.j[i];
+        const int64_t a = (int64_t)p.mpad * p.kpad, b = p.wd ? (int64_t)p.mpad_d * p.kpad_d : 0;
+        n = a > n ? a : n;
+        n = b > n ? b : n;
+    }
+    hipLaunchKernelGGL(k_prep_weights_all, dim3(blocks_for(n, 256), jobs.n), dim3(256), 0, st, jobs);
     return hipGetLastError();
 }
 
@@ -1177,7 +1219,7 @@ hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint1
 }
 
 hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st) {
+                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st, BiasJob* defer) {
     // c channels of partial sums per work-group fit the 64-float rows of part
     if (c <= 0 || c > 64 || 256 % c != 0 || cout_param > c) return hipErrorInvalidValue;
     const bool vec = c % 4 == 0 && ldg % 4 == 0 && offg % 4 == 0 && ((uintptr_t)g & 15) == 0 &&
@@ -1196,6 +1238,10 @@ hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int 
     else
         hipLaunchKernelGGL(k_grad_relu_cast, dim3((unsigned)nb), dim3(256), 0, st, g, ldg, offg, act, lda, offa, c,
                            total, per, out, part);
+    if (defer) {   // the caller reduces the partials later (conv_wgrad of the same layer)
+        *defer = BiasJob{part, (int)nb, cout_param, db};
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_bias_reduce, dim3(cout_param), dim3(256), 0, st, part, (int)nb, db);
     return hipGetLastError();
 }

@@ -208,8 +208,9 @@ hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, cons
     const Level& L = net->lev[LAYERS[li].level];
     const int64_t tot = L.vox();
     float* grad = net->at<float>(net->o_grad);
+    nd::BiasJob bias;
     hipError_t e = nd::grad_relu_cast(g, ldg, offg, LAYERS[li].relu ? act : nullptr, lda, offa, G.cout, tot, packed,
-                                      net->at<float>(net->o_bpart), G.cout_param, grad + G.off_b, net->stream);
+                                      net->at<float>(net->o_bpart), G.cout_param, grad + G.off_b, net->stream, &bias);
     if (e != hipSuccess) return e;
     // weight gradient
     nd::WgradArgs w;
@@ -226,7 +227,7 @@ hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, cons
     w.cxo = cxo;
     w.chunk = wgrad_chunk(tot);
     const int nchunks = (int)((tot + w.chunk - 1) / w.chunk);
-    e = nd::conv_wgrad(w, G.mt, nchunks, G.cout_param, grad + G.off_w, net->stream);
+    e = nd::conv_wgrad(w, G.mt, nchunks, G.cout_param, grad + G.off_w, net->stream, &bias);
     if (e != hipSuccess) return e;
     if (!dx) return hipSuccess;
     // input gradient: the forward kernel with the flipped, transposed weights
@@ -247,13 +248,16 @@ hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, cons
 int prepare_weights(lbmnet* net) {
     if (!net->weights_dirty) return LBM_OK;
     const float* master = net->at<float>(net->o_master);
+    static_assert(LBMNET_LAYERS <= nd::MAX_PREP_JOBS, "one packing launch covers every layer");
+    nd::PrepJobs jobs{};
+    jobs.n = LBMNET_LAYERS;
     for (int i = 0; i < LBMNET_LAYERS; ++i) {
         const LayerGeom& g = net->lg[i];
-        HIP_TRY(nd::prep_weights(master + g.off_w, g.cin, g.cout_param, g.cout, net->at<uint16_t>(net->o_wt[i]),
-                                 g.mpad, g.kpad, net->train ? net->at<uint16_t>(net->o_wd[i]) : nullptr, g.mpad_d,
-                                 g.kpad_d, net->stream),
-                "lbmnet weight packing");
+        jobs.j[i] = nd::PrepJob{master + g.off_w, net->at<uint16_t>(net->o_wt[i]),
+                                net->train ? net->at<uint16_t>(net->o_wd[i]) : nullptr, g.cin, g.cout_param, g.cout,
+                                g.mpad, g.kpad, g.mpad_d, g.kpad_d};
     }
+    HIP_TRY(nd::prep_weights_all(jobs, net->stream), "lbmnet weight packing");
     net->weights_dirty = false;
     return LBM_OK;
 }

@@ -37,14 +37,43 @@ struct WgradArgs {
     int64_t chunk;   // voxels per partial, multiple of 16
 };
 
+// Bias-gradient partials waiting for their reduction: part [nparts][64],
+// channels < cout_param summed into db.
+struct BiasJob {
+    const float* part;
+    int nparts, cout_param;
+    float* db;
+};
+
+// FP32 master weights of one layer packed to the BF16 forward (wt) and
+// input-gradient (wd, may be null) matrices; see prep_weights.
+struct PrepJob {
+    const float* w;
+    uint16_t* wt;
+    uint16_t* wd;
+    int cin, cout_param, cout, mpad, kpad, mpad_d, kpad_d;
+};
+constexpr int MAX_PREP_JOBS = 16;
+struct PrepJobs {
+    PrepJob j[MAX_PREP_JOBS];
+    int n;
+};
+
 hipError_t conv_forward(const ConvArgs& a, int mt, bool f32out, hipStream_t st);
-hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st);
+// bias (may be null): a deferred bias-gradient reduction, done in the same
+// launch as the weight-gradient reduction.
+hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, float* dw, hipStream_t st,
+                      const BiasJob* bias = nullptr);
 hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint16_t* wt, int mpad, int kpad,
                         uint16_t* wd, int mpad_d, int kpad_d, hipStream_t st);
+hipError_t prep_weights_all(const PrepJobs& jobs, hipStream_t st);
 // Masked gradient (in place), its packed BF16 copy and the bias gradient db
 // (channels < cout_param).  part: FP32 scratch of BIAS_PARTS * 64 values.
+// defer non-null: the bias reduction is not launched but described in
+// *defer (for conv_wgrad); part must then stay untouched until it runs.
 hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st);
+                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st,
+                          BiasJob* defer = nullptr);
 hipError_t cast_input(const float* x, int64_t count, uint16_t* out, hipStream_t st);
 hipError_t avgpool_fwd(const uint16_t* x, int ld, int off, int c, int n, int d, int h, int w, uint16_t* y,
                        hipStream_t st);
