@@ -479,16 +479,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
         }
 }
 
-// --- weight gradient, one output tile of 16 channels, waves split the brick -------
-// For cout <= 16 and cin a multiple of 16.  Work-group (p, yb) covers input
-// channels 16 yb .. 16 yb + 15 and all 27 taps (27 N-tiles) over the bricks
-// p, p + P, ...; wave w takes the z-slice w of every brick (64 voxels, four
-// K-steps of 16).  For one (dz, dy) the B fragments of dx = 0, 1, 2 are
-// windows of six consecutive halo values starting at an even index, so
-// three aligned 4-byte LDS reads give all three (dx = 1 by a 16-bit funnel
-// shift): 27 MFMAs per K-step for 28 LDS reads, against 7 MFMAs for 29 reads
-// when the waves split the taps.  The four waves' sums are added in LDS in
-// a fixed order (wave 3, 2, 1, 0) before the partial is written.
+// --- weight gradient, 16 x 16 channel tiles, waves split the brick --------------
+// For cin a multiple of 16 and cout <= 16 MT.  Work-group (p, y) covers input
+// channels 16 (y % (cin / 16)) + 0 .. 15, output channels 16 (y / (cin / 16))
+// + 0 .. 15 and all 27 taps (27 N-tiles) over the bricks p, p + P, ...; wave
+// w takes the z-slice w of every brick (64 voxels, two K-steps of 32).  For
+// one (dz, dy) the B fragments of dx = 0, 1, 2 are windows of consecutive
+// halo values starting at an even index, so five aligned 4-byte LDS reads
+// give all three (dx = 1 by 16-bit funnel shifts).  The four waves' sums are
+// added in LDS in a fixed order (wave 3, 2, 1, 0) before the partial is
+// written.
 template <int CIN>
 __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts) {
     constexpr int NHALO = HZ * HY * HX;
@@ -505,8 +505,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
     const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
     const int64_t nbricks = (int64_t)a.n * tx * ty * tz;
     const int64_t V = (int64_t)a.d * a.h * a.w;
-    const int gq = a.cout >> 2;
-    const int c0 = 16 * (int)blockIdx.y;   // first input channel of this work-group
+    constexpr int CG = CIN / 16;                       // input channel groups
+    const int c0 = 16 * ((int)blockIdx.y % CG);        // first input channel of this work-group
+    const int co0 = 16 * ((int)blockIdx.y / CG);       // first output channel of this work-group
+    const int gq = (a.cout - co0) >> 2 < 4 ? (a.cout - co0) >> 2 : 4;   // 4-channel gradient pieces
     for (int k = threadIdx.x; k < 16 * NB; k += 256) gy[k] = 0;   // rows co >= cout stay zero
     v4f acc[27];
 #pragma unroll
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
         const int v = threadIdx.x;
         const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
         const int64_t g = sbase + ((int64_t)(zs + 1 + vz) * a.h + (ys + 1 + vy)) * a.w + (xs + 1 + vx);
-        const uint2* gsrc = (const uint2*)(a.dy + g * a.ldy);
+        const uint2* gsrc = (const uint2*)(a.dy + g * a.ldy + co0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) greg[k] = k < gq ? gsrc[k] : uint2{0u, 0u};
     };
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
     for (int t = 0; t < 27; ++t) {
         const int n = t * CIN + c0 + r16;   // column of (tap t, input channel c0 + r16)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) part[(4 * q + j) * a.npad + n] = acc[t][j];
+        for (int j = 0; j < 4; ++j) part[(co0 + 4 * q + j) * a.npad + n] = acc[t][j];
     }
 }
 
@@ -1167,15 +1169,12 @@ hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, f
     const int nparts = (int)(nbricks < nchunks ? nbricks : nchunks);
     hipError_t e;
     int nred = nparts;   // partials the reduction sums
-    if (bricks && mt == 1 && a.cin % 16 == 0 && a.cin <= 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
-        const dim3 grid(nparts, a.cin / 16);
+    if (bricks && (mt == 1 || mt == 2) && a.mpad >= 16 * mt && a.cin % 16 == 0 && a.cin <= 32 && a.ldx % 8 == 0 &&
+        a.cxo % 8 == 0) {
+        const dim3 grid(nparts, a.cin / 16 * mt);   // (input group, output group) pairs
         if (a.cin == 16) hipLaunchKernelGGL(k_conv_wgrad_k16<16>, grid, dim3(256), 0, st, a, nparts);
         else hipLaunchKernelGGL(k_conv_wgrad_k16<32>, grid, dim3(256), 0, st, a, nparts);
         e = hipGetLastError();
-    } else if (bricks && a.cin == 16 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
-        e = wgrad_lds<16>(a, mt, nparts, st);
-    } else if (bricks && a.cin == 32 && a.ldx % 8 == 0 && a.cxo % 8 == 0) {
-        e = wgrad_lds<32>(a, mt, nparts, st);
     } else if (bricks && a.cin == 4 && a.ldx % 4 == 0 && a.cxo % 4 == 0) {
         e = wgrad_lds<4>(a, mt, nparts, st);
     } else {
