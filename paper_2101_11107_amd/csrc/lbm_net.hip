@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lbm_net_internal.h"
 
@@ -140,18 +141,26 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvArgs a) {
     const int xs = bx * BX - 1, ys = by * BY - 1, zs = bz * BZ - 1;   // halo origin
     const int64_t V = (int64_t)a.d * a.h * a.w;
     const int64_t sbase = (int64_t)s * V;
-    for (int idx = threadIdx.x; idx < NHALO * PPV; idx += 256) {
+    // every staging load of the thread is issued before the first LDS store
+    constexpr int HITER = (NHALO * PPV + 255) / 256;
+    using Piece = typename std::conditional<PIECE == 16, uint4, uint2>::type;
+    Piece pc[HITER];
+#pragma unroll
+    for (int i = 0; i < HITER; ++i) {
+        const int idx = (int)threadIdx.x + 256 * i;
         const int vox = idx / PPV, p = idx - vox * PPV;
         const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
         const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
-        const bool in = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
+        const bool in = idx < NHALO * PPV && xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
         const uint16_t* src = a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + p * (PIECE / 2);
-        uint16_t* dst = tile + vox * CIN + p * (PIECE / 2);
-        if constexpr (PIECE == 16) {
-            *(uint4*)dst = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
-        } else {
-            *(uint2*)dst = in ? *(const uint2*)src : uint2{0u, 0u};
-        }
+        pc[i] = in ? *(const Piece*)src : Piece{};
+    }
+#pragma unroll
+    for (int i = 0; i < HITER; ++i) {
+        const int idx = (int)threadIdx.x + 256 * i;
+        if (idx >= NHALO * PPV) continue;
+        const int vox = idx / PPV, p = idx - vox * PPV;
+        *(Piece*)(tile + vox * CIN + p * (PIECE / 2)) = pc[i];
     }
     __syncthreads();
     v4f acc[MT][4];
