@@ -736,11 +736,12 @@ __global__ void k_prep_weights_all(PrepJobs jobs) {
 }
 
 // g (FP32, channels [off, off + c) of rows of length ld) times the ReLU mask of
-// act (BF16, same layout; null: no mask), written in place and as a packed
-// BF16 copy [v][c]; per work-group channel sums of the masked FP32 values go to
+// act (BF16, same layout; null: no mask), written as a packed BF16 copy
+// [v][c] (g itself is only read); per work-group channel sums of the masked
+// FP32 values go to
 // part[block][0..c) for the bias gradient.  c divides 256 and `per` (elements
 // per work-group) is a multiple of 256, so a thread always sees one channel.
-__global__ __launch_bounds__(256) void k_grad_relu_cast(float* __restrict__ g, int ldg, int offg,
+__global__ __launch_bounds__(256) void k_grad_relu_cast(const float* __restrict__ g, int ldg, int offg,
                                                         const uint16_t* __restrict__ act, int lda, int offa, int c,
                                                         int64_t total, int64_t per, uint16_t* __restrict__ out,
                                                         float* __restrict__ part) {
@@ -771,9 +772,7 @@ __global__ __launch_bounds__(256) void k_grad_relu_cast(float* __restrict__ g, i
         for (int u = 0; u < U; ++u) {
             const int64_t idx = i0 + 256 * u;
             if (idx >= e1) break;
-            const int64_t v = idx >> csh;
             const float x = keep[u] ? val[u] : 0.0f;
-            g[v * ldg + offg + ch] = x;
             out[idx] = f2bf(x);
             acc += x;
         }
@@ -790,7 +789,7 @@ __global__ __launch_bounds__(256) void k_grad_relu_cast(float* __restrict__ g, i
 // The same with four consecutive channels per thread (16-byte FP32 and 8-byte
 // BF16 accesses): c % 4 == 0, rows and offsets multiples of 4, `per` a
 // multiple of 1024, so thread t always sees channels 4t mod c .. +3.
-__global__ __launch_bounds__(256) void k_grad_relu_cast4(float* __restrict__ g, int ldg, int offg,
+__global__ __launch_bounds__(256) void k_grad_relu_cast4(const float* __restrict__ g, int ldg, int offg,
                                                          const uint16_t* __restrict__ act, int lda, int offa, int c,
                                                          int64_t total, int64_t per, uint16_t* __restrict__ out,
                                                          float* __restrict__ part) {
@@ -816,7 +815,6 @@ __global__ __launch_bounds__(256) void k_grad_relu_cast4(float* __restrict__ g, 
         for (int u = 0; u < U; ++u) {
             const int64_t idx = i0 + 1024 * u;
             if (idx >= e1) break;
-            const int64_t v = idx >> csh;
             float x[4] = {val[u].x, val[u].y, val[u].z, val[u].w};
             if (act) {
                 const uint16_t mk[4] = {(uint16_t)(m[u].x & 0xffffu), (uint16_t)(m[u].x >> 16),
@@ -825,7 +823,6 @@ __global__ __launch_bounds__(256) void k_grad_relu_cast4(float* __restrict__ g, 
                 for (int j = 0; j < 4; ++j)
                     if (!(bf2f(mk[j]) > 0.0f)) x[j] = 0.0f;
             }
-            *(float4*)(g + v * ldg + offg + ch0) = float4{x[0], x[1], x[2], x[3]};
             const uint32_t lo = (uint32_t)f2bf(x[0]) | ((uint32_t)f2bf(x[1]) << 16);
             const uint32_t hi = (uint32_t)f2bf(x[2]) | ((uint32_t)f2bf(x[3]) << 16);
             *(uint2*)(out + idx) = uint2{lo, hi};
@@ -1226,8 +1223,9 @@ hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint1
     return hipGetLastError();
 }
 
-hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st, BiasJob* defer) {
+hipError_t grad_relu_cast(const float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c,
+                          int64_t total, uint16_t* out, float* part, int cout_param, float* db, hipStream_t st,
+                          BiasJob* defer) {
     // c channels of partial sums per work-group fit the 64-float rows of part
     if (c <= 0 || c > 64 || 256 % c != 0 || cout_param > c) return hipErrorInvalidValue;
     const bool vec = c % 4 == 0 && ldg % 4 == 0 && offg % 4 == 0 && ((uintptr_t)g & 15) == 0 &&

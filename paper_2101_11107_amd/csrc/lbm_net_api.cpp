@@ -200,7 +200,8 @@ hipError_t conv_layer(lbmnet* net, int li, const uint16_t* x, int ldx, int cxo, 
 }
 
 // Backward of layer li.  g: FP32 gradient with respect to the layer output
-// (row ldg, channel offset offg), masked by the ReLU of act in place.  x: the
+// (row ldg, channel offset offg), masked by the ReLU of act (g is only read;
+// the masked values go to the packed BF16 copy).  x: the
 // layer input.  dx: FP32 gradient with respect to the input (null: skipped).
 hipError_t backward_layer(lbmnet* net, int li, float* g, int ldg, int offg, const uint16_t* act, int lda, int offa,
                           const uint16_t* x, int ldx, int cxo, uint16_t* packed, float* dx, int lddx) {
@@ -515,7 +516,7 @@ int lbmnet_destroy(lbmnet* net) {
 
 namespace {
 struct ConvWork {
-    size_t xb, yb, wt, wd, g, gb, wpart, bpart, total;
+    size_t xb, yb, wt, wd, gb, wpart, bpart, total;
 };
 bool conv_sizes_ok(int n, int d, int h, int w, int cin, int cout) {
     return n >= 1 && d >= 1 && h >= 1 && w >= 16 && w % 16 == 0 && cin >= 4 && cin <= 32 && cin % 4 == 0 &&
@@ -537,7 +538,6 @@ ConvWork conv_work(int n, int d, int h, int w, int cin, int cout) {
     c.yb = take(2 * V * cout);
     c.wt = take(2 * (size_t)mpad * kpad);
     c.wd = take(2 * (size_t)mpad_d * kpad_d);
-    c.g = take(4 * V * cout);
     c.gb = take(2 * V * cout);
     c.wpart = take(4 * (size_t)nchunks * mpad * ceil16(27 * cin));
     c.bpart = take(4 * 64 * (size_t)nd::BIAS_PARTS);
@@ -571,7 +571,6 @@ int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const
     uint16_t* yb = (uint16_t*)(base + cw.yb);
     uint16_t* wt = (uint16_t*)(base + cw.wt);
     uint16_t* wd = (uint16_t*)(base + cw.wd);
-    float* g = (float*)(base + cw.g);
     uint16_t* gb = (uint16_t*)(base + cw.gb);
     HIP_TRY(nd::cast_input(x, V * cin, xb, st), "lbmnet_conv3d cast");
     HIP_TRY(nd::prep_weights(wts, cin, cout, cout, wt, mpad, kpad, wd, mpad_d, kpad_d, st), "lbmnet_conv3d weights");
@@ -588,8 +587,7 @@ int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const
     if (!dy) return LBM_OK;
     a.y = yb;
     HIP_TRY(nd::conv_forward(a, mt, false, st), "lbmnet_conv3d forward (BF16 copy)");
-    HIP_TRY(hipMemcpyAsync(g, dy, sizeof(float) * V * cout, hipMemcpyDeviceToDevice, st), "lbmnet_conv3d copy");
-    HIP_TRY(nd::grad_relu_cast(g, cout, 0, relu ? yb : nullptr, cout, 0, cout, V, gb, (float*)(base + cw.bpart), cout,
+    HIP_TRY(nd::grad_relu_cast(dy, cout, 0, relu ? yb : nullptr, cout, 0, cout, V, gb, (float*)(base + cw.bpart), cout,
                                db, st),
             "lbmnet_conv3d mask and bias gradient");
     nd::WgradArgs wa;

@@ -67,12 +67,13 @@ hipError_t conv_wgrad(const WgradArgs& a, int mt, int nchunks, int cout_param, f
 hipError_t prep_weights(const float* w, int cin, int cout_param, int cout, uint16_t* wt, int mpad, int kpad,
                         uint16_t* wd, int mpad_d, int kpad_d, hipStream_t st);
 hipError_t prep_weights_all(const PrepJobs& jobs, hipStream_t st);
-// Masked gradient (in place), its packed BF16 copy and the bias gradient db
-// (channels < cout_param).  part: FP32 scratch of BIAS_PARTS * 64 values.
-// defer non-null: the bias reduction is not launched but described in
-// *defer (for conv_wgrad); part must then stay untouched until it runs.
-hipError_t grad_relu_cast(float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c, int64_t total,
-                          uint16_t* out, float* part, int cout_param, float* db, hipStream_t st,
+// The gradient g masked by the ReLU of act, as a packed BF16 copy (g itself
+// is only read), and the bias gradient db (channels < cout_param).  part:
+// FP32 scratch of BIAS_PARTS * 64 values.  defer non-null: the bias
+// reduction is not launched but described in *defer (for conv_wgrad); part
+// must then stay untouched until it runs.
+hipError_t grad_relu_cast(const float* g, int ldg, int offg, const uint16_t* act, int lda, int offa, int c,
+                          int64_t total, uint16_t* out, float* part, int cout_param, float* db, hipStream_t st,
                           BiasJob* defer = nullptr);
 hipError_t cast_input(const float* x, int64_t count, uint16_t* out, hipStream_t st);
 hipError_t avgpool_fwd(const uint16_t* x, int ld, int off, int c, int n, int d, int h, int w, uint16_t* y,
