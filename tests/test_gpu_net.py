@@ -107,6 +107,38 @@ def test_conv_layer_matches_oracle(cin, cout, relu, dims):
         assert np.all(err <= bound), name
 
 
+@pytest.mark.parametrize("cin,cout", [(16, 16), (32, 32), (4, 16)])
+def test_conv_layer_repeats_bit_for_bit_with_several_bricks_per_work_group(cin, cout):
+    """Every output of a layer's forward and backward is the same bits on a
+    second call: the weight-gradient kernels walk a fixed brick sequence per
+    work-group and add the waves' and the partials' sums in a fixed order."""
+    torch = _torch()
+    from paper_2101_11107_amd import net as nn
+    n, d, h, w = 1, 32, 64, 128
+    print(f"case conv layer repeat cin {cin} cout {cout}", flush=True)
+    rng = np.random.default_rng(cin + 7 * cout)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.float32))).to(dev)
+    xd = T(rng.normal(size=(n, d, h, w, cin)))
+    wd = T(rng.normal(size=(cout, 27, cin)) / np.sqrt(27 * cin))
+    bd = T(rng.normal(0, 0.1, cout))
+    dyd = T(rng.normal(size=(n, d, h, w, cout)))
+    ws = nn.lbmnet_conv3d_workspace(n, d, h, w, cin, cout)
+    work = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
+    off = (-work.data_ptr()) % 256
+    work = work[off: off + ws]
+    st = torch.cuda.current_stream().cuda_stream
+    outs = []
+    for _ in range(2):
+        o = (torch.empty((n, d, h, w, cout), dtype=torch.float32, device=dev), torch.empty_like(xd),
+             torch.empty_like(wd), torch.empty_like(bd))
+        nn.lbmnet_conv3d(n, d, h, w, cin, cout, 1, xd, wd, bd, dyd, *o, work, st)
+        outs.append(o)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("y", "dx", "dw", "db"), outs[0], outs[1]):
+        assert torch.equal(a, b), name
+
+
 def _net_inputs(seed, n, d, h, w):
     rng = np.random.default_rng(seed)
     x = np.concatenate([rng.normal(0, 0.6, (n, d, h, w, 3)), (rng.random((n, d, h, w, 1)) > 0.3)],
