@@ -829,12 +829,21 @@ int lbm_step(lbm_domain* d, int nsteps) {
     int left = nsteps;
     // Long runs replay captured graphs of GRAPH_STEPS launches (no host launch
     // gaps); the default (NULL) stream cannot be captured and runs eagerly.
+    // The graphs of both buffer parities are captured together, on the first
+    // call after a change that dropped them, so a later call (a timed run)
+    // never waits for a capture, whatever parity it starts at.
     if (d->stream != nullptr) {
-        while (left >= GRAPH_STEPS) {
-            if (!d->graph[d->cur]) {
+        if (nsteps > 0 && (!d->graph[0] || !d->graph[1])) {
+            const int cur = d->cur;
+            for (int par = 0; par < 2 && rc == 0; ++par) {
+                if (d->graph[par]) continue;
+                d->cur = par;
                 rc = build_graph(d);
-                if (rc) return rc;
             }
+            d->cur = cur;
+            if (rc) return rc;
+        }
+        while (left >= GRAPH_STEPS) {
             HIP_TRY(hipGraphLaunch(d->graph[d->cur], d->stream), "graph launch");
             left -= GRAPH_STEPS;
         }
