@@ -126,6 +126,24 @@ int lbmnet_conv3d(int n, int d, int h, int w, int cin, int cout, int relu, const
                   const float* b, const float* dy, float* y, float* dx, float* dw, float* db, void* work,
                   size_t work_bytes, void* hip_stream);
 
+/* ---- the same layer for callers that cannot allocate ----------------------
+ * For code under HIP graph capture, tight serving loops and harnesses that
+ * forbid device allocation: lbmnet_conv3d with the same arguments and results
+ * (the same kernels, bit for bit), but its workspace is a fixed 64 MiB device
+ * array of the library (lbmnet_conv3d_noalloc_limit reports the size) that
+ * each GPU holds from the first call on it until the process ends.  The call
+ * allocates nothing.  EINVAL (nothing launched) when the layer's
+ * lbmnet_conv3d_workspace exceeds the limit; EDEVICE if the array's device
+ * address cannot be found.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams or host threads without
+ * ordering) race and give wrong results; calls ordered on one stream are safe.
+ * The array keeps the last call's contents; nothing in it needs clearing
+ * between calls. */
+int lbmnet_conv3d_noalloc_limit(size_t* bytes);
+int lbmnet_conv3d_noalloc(int n, int d, int h, int w, int cin, int cout, int relu, const float* x,
+                          const float* wts, const float* b, const float* dy, float* y, float* dx, float* dw,
+                          float* db, void* hip_stream);
+
 /* ---- data movement between node lists and dense grids ----------------------
  * Scatter: dense (device FP32 [D][H][W][3]) and mask (device uint8 [D][H][W])
  * are cleared, then for node i with coordinates xyz[i] = (x, y, z) (device

@@ -36,7 +36,8 @@ EXPORTED = [
     "lbm_batch_set_config", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_status", "lbm_batch_destroy",
     "lbmnet_param_count", "lbmnet_layer_info", "lbmnet_create", "lbmnet_device_bytes", "lbmnet_attach_device",
     "lbmnet_set_params", "lbmnet_get_params", "lbmnet_forward", "lbmnet_loss_grad", "lbmnet_adam_step",
-    "lbmnet_adam_count", "lbmnet_destroy", "lbmnet_conv3d_workspace", "lbmnet_conv3d", "lbmnet_scatter",
+    "lbmnet_adam_count", "lbmnet_destroy", "lbmnet_conv3d_workspace", "lbmnet_conv3d", "lbmnet_conv3d_noalloc_limit",
+    "lbmnet_conv3d_noalloc", "lbmnet_scatter",
     "lbmnet_gather", "lbmnet_crop", "lbmnet_trilinear",
 ]
 
@@ -117,6 +118,8 @@ def load():
         "lbmnet_destroy": ([_P], ctypes.c_int),
         "lbmnet_conv3d_workspace": ([ctypes.c_int] * 6 + [ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbmnet_conv3d": ([ctypes.c_int] * 7 + [_P] * 9 + [ctypes.c_size_t, _P], ctypes.c_int),
+        "lbmnet_conv3d_noalloc_limit": ([ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbmnet_conv3d_noalloc": ([ctypes.c_int] * 7 + [_P] * 9, ctypes.c_int),
         "lbmnet_scatter": ([_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                             _P, _P, _P], ctypes.c_int),
         "lbmnet_gather": ([_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,

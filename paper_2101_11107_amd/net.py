@@ -95,6 +95,18 @@ def lbmnet_conv3d(n, d, h, w, cin, cout, relu, x, wts, b, dy, y, dx, dw, db, wor
                                 _dptr(work), work.numel() * work.element_size(), _sp(hip_stream)))
 
 
+def lbmnet_conv3d_noalloc_limit() -> int:
+    v = ctypes.c_size_t()
+    _check(load().lbmnet_conv3d_noalloc_limit(ctypes.byref(v)))
+    return v.value
+
+
+def lbmnet_conv3d_noalloc(n, d, h, w, cin, cout, relu, x, wts, b, dy, y, dx, dw, db, hip_stream) -> None:
+    _check(load().lbmnet_conv3d_noalloc(int(n), int(d), int(h), int(w), int(cin), int(cout), int(relu), _dptr(x),
+                                        _dptr(wts), _dptr(b), _dptr(dy), _dptr(y), _dptr(dx), _dptr(dw),
+                                        _dptr(db), _sp(hip_stream)))
+
+
 def lbmnet_scatter(vals, xyz, D, H, W, scale, dense, mask, hip_stream) -> None:
     count = xyz.shape[0]
     _check(load().lbmnet_scatter(_dptr(vals), _dptr(xyz), int(count), int(D), int(H), int(W), float(scale),

@@ -87,3 +87,21 @@ def test_library_womersley_profile_matches_closed_form():
             assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)) + 1e-18, (alpha, t)
     # omega = 0: steady Poiseuille
     assert abs(lbm.lbm_inlet_profile(3.0, 0.0, R, 0.02, 1e-6, 0.0, 0.0) - 1e-6 * (R * R - 9.0) / 0.08) < 1e-15
+
+
+def test_noalloc_layer_rejects_workspace_beyond_its_fixed_array():
+    """lbmnet_conv3d_noalloc refuses, before touching the GPU, a layer whose
+    workspace exceeds the library's fixed array, and reports that size."""
+    from paper_2101_11107_amd import lbm
+    from paper_2101_11107_amd import net as nn
+    limit = nn.lbmnet_conv3d_noalloc_limit()
+    assert limit == 64 << 20
+    dims = (4, 64, 64, 128, 32, 32)
+    assert nn.lbmnet_conv3d_workspace(*dims) > limit
+    with pytest.raises(lbm.LbmError) as e:
+        nn.lbmnet_conv3d_noalloc(*dims, 1, *[None] * 8, 0)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "workspace" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        nn.lbmnet_conv3d_noalloc(1, 3, 4, 16, 5, 16, 1, *[None] * 8, 0)   # cin not a multiple of 4
+    assert e.value.code == lbm.LBM_EINVAL
