@@ -276,6 +276,26 @@ class O1State:
         return self.case.rates
 
 
+def moving_wall_value(src: np.ndarray, feq_a: np.ndarray, feq_b: np.ndarray) -> np.ndarray:
+    """Velocity inlet, moving-wall bounce-back (reading C8): the population that
+    returns to the node is the one that left it towards the wall, plus
+    f_eq_abar(1, u_w) - f_eq_a(1, u_w); a the direction into the wall."""
+    return src + feq_b - feq_a
+
+
+def anti_bounce_back_value(src: np.ndarray, feq_a: np.ndarray, feq_b: np.ndarray) -> np.ndarray:
+    """Pressure outlet, anti-bounce-back (reading C9): minus the population
+    that left towards the outlet, plus f_eq_a + f_eq_abar at (rho_out, u(x))."""
+    return -src + feq_b + feq_a
+
+
+def wall_force_of_links(src: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """Momentum handed to the wall per step by halfway bounce-back links that
+    leave with post-collision populations src in direction c: each reverses,
+    so the fluid loses 2 f* c (momentum exchange)."""
+    return 2.0 * src.sum() * c
+
+
 def stream(state: O1State, f_post_nodes: np.ndarray, u_nodes: np.ndarray) -> tuple:
     """Push streaming of post-collision populations with the boundary rules.
 
@@ -320,7 +340,7 @@ def stream(state: O1State, f_post_nodes: np.ndarray, u_nodes: np.ndarray) -> tup
         # walls
         sel = kind == 0
         new[fl[sel, 0], fl[sel, 1], fl[sel, 2], b] = src[sel]
-        fwall += 2.0 * src[sel].sum() * C[a].astype(np.float64)
+        fwall += wall_force_of_links(src[sel], C[a].astype(np.float64))
         # inlet ghosts
         sel = kind == 2
         if np.any(sel):
@@ -329,7 +349,7 @@ def stream(state: O1State, f_post_nodes: np.ndarray, u_nodes: np.ndarray) -> tup
             mid = fl[sel][:, ::-1].astype(np.float64) + 0.5 * C[a][None, :]
             uw = inlet_velocity(mid, state.t, case.inlet, nu)
             feq = equilibrium_series(np.ones(len(uw)), uw)
-            val = src[sel] + feq[:, b] - feq[:, a]
+            val = moving_wall_value(src[sel], feq[:, a], feq[:, b])
             new[fl[sel, 0], fl[sel, 1], fl[sel, 2], b] = val
             q_in += float((val - src[sel]).sum())
         # outlet ghosts
@@ -337,7 +357,7 @@ def stream(state: O1State, f_post_nodes: np.ndarray, u_nodes: np.ndarray) -> tup
         if np.any(sel):
             ux = u_nodes[sel]
             feq = equilibrium_series(np.full(len(ux), case.rho_out), ux)
-            val = -src[sel] + feq[:, b] + feq[:, a]
+            val = anti_bounce_back_value(src[sel], feq[:, a], feq[:, b])
             new[fl[sel, 0], fl[sel, 1], fl[sel, 2], b] = val
             q_out += float((val - src[sel]).sum())
     return new, fwall, q_in, q_out

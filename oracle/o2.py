@@ -15,15 +15,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "o2_fast.c")
 _LIB = os.path.join(_HERE, "_o2.so")
+# The same source built with long double arithmetic (x87 80-bit on x86-64),
+# used only to measure the rounding floor of the double build.
+_LIB_LD = os.path.join(_HERE, "_o2_ld.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (plain -O2, OpenMP, IEEE semantics)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the C oracle with gcc (plain -O2, OpenMP, IEEE semantics), in
+    double and in long double."""
+    for lib, extra in ((_LIB, []), (_LIB_LD, ["-DO2_LONG_DOUBLE"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                                   "-fno-fast-math", "-ffp-contract=off", *extra, _SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -38,33 +43,34 @@ class _Case(ctypes.Structure):
                 ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("collision", ctypes.c_int)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(long_double: bool = False):
+    if long_double not in _libs:
+        path = _LIB_LD if long_double else _LIB
+        if not os.path.exists(path):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.o2_collide.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_int]
         lib.o2_stream.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, ctypes.c_int, P]
         lib.o2_run.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_int, P,
                                ctypes.c_int, P]
         lib.o2_mass_momentum.argtypes = [ctypes.c_int64, P, P]
-        _lib = lib
-    return _lib
+        _libs[long_double] = lib
+    return _libs[long_double]
 
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _weights():
-    w1 = {-1: 1.0 / 6.0, 0: 2.0 / 3.0, 1: 1.0 / 6.0}
+def _weights(real=np.float64):
+    one, two, three, six = (real(v) for v in (1, 2, 3, 6))
+    w1 = {-1: one / six, 0: two / three, 1: one / six}
     return np.array([w1[cx] * w1[cy] * w1[cz] for cz in (-1, 0, 1) for cy in (-1, 0, 1)
-                     for cx in (-1, 0, 1)])
+                     for cx in (-1, 0, 1)], dtype=real)
 
 
 class O2Sim:
@@ -80,9 +86,12 @@ class O2Sim:
     bounce-back.
     """
 
-    def __init__(self, case, nthreads: int = 0, rates5=None, g_time=None, wall_q=None):
+    def __init__(self, case, nthreads: int = 0, rates5=None, g_time=None, wall_q=None,
+                 long_double: bool = False):
         self.case = case
-        self.lib = _load()
+        self.lib = _load(long_double)
+        # populations, velocities and monitors in the build's real type
+        self.real = np.longdouble if long_double else np.float64
         nz, ny, nx = case.mask.shape
         self.mask = np.ascontiguousarray(case.mask, np.uint8)
         zyx = np.argwhere(self.mask == 1)
@@ -115,17 +124,17 @@ class O2Sim:
         self.c = c
         self.wq = None
         if wall_q is not None:
-            self.wq = np.full((self.n, 27), 0.5)
+            self.wq = np.full((self.n, 27), 0.5, dtype=self.real)
             for (x, y, z, a), q in wall_q.items():
                 k = self.idx[(z * ny + y) * nx + x]
                 if k < 0:
                     raise ValueError(f"wall link at a non-fluid cell {(x, y, z)}")
                 self.wq[k, a] = float(q)
-        self.f = np.tile(_weights()[None, :], (self.n, 1))
-        self.fpost = np.zeros((self.n, 27))
-        self.u = np.zeros((self.n, 3))
+        self.f = np.tile(_weights(self.real)[None, :], (self.n, 1))
+        self.fpost = np.zeros((self.n, 27), self.real)
+        self.u = np.zeros((self.n, 3), self.real)
         self.t = 0
-        self.monitors = np.zeros(10)
+        self.monitors = np.zeros(10, self.real)
 
     def run(self, nsteps: int) -> np.ndarray:
         rc = self.lib.o2_run(ctypes.byref(self.c), _ptr(self.mask), _ptr(self.coords), _ptr(self.idx),
@@ -146,9 +155,9 @@ class O2Sim:
 
     def stream_from_post(self, fpost: np.ndarray, u: np.ndarray, t: int) -> np.ndarray:
         """Push-stream the given post-collision state of time t; sets f = f(t+1)."""
-        fpost = np.ascontiguousarray(fpost, np.float64)
-        u = np.ascontiguousarray(u, np.float64)
-        mon5 = np.zeros(5)
+        fpost = np.ascontiguousarray(fpost, self.real)
+        u = np.ascontiguousarray(u, self.real)
+        mon5 = np.zeros(5, self.real)
         rc = self.lib.o2_stream(ctypes.byref(self.c), _ptr(self.mask), _ptr(self.coords), _ptr(self.idx),
                                 self.n, _ptr(fpost), _ptr(u), _ptr(self.f), int(t), _ptr(mon5),
                                 self.nthreads, self._wq())

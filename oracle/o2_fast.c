@@ -40,6 +40,19 @@
 #include <string.h>
 #include <omp.h>
 
+/* Real type of the oracle's arithmetic.  double by default; built with
+ * -DO2_LONG_DOUBLE every population, moment, equilibrium and sum is long
+ * double (the x87 80-bit format with gcc on x86-64), which measures the
+ * rounding floor of the double build.  Case parameters and the inlet profile
+ * stay double: they are inputs. */
+#ifdef O2_LONG_DOUBLE
+typedef long double real;
+#define RC(x) x##L
+#else
+typedef double real;
+#define RC(x) x
+#endif
+
 typedef struct {
     int nx, ny, nz;
     unsigned periodic;          /* bit0 x, bit1 y, bit2 z */
@@ -54,13 +67,13 @@ typedef struct {
 } o2_case;
 
 static int CXYZ[27][3];
-static double WGT[27];
+static real WGT[27];
 static int OPPD[27];
 static int tables_ready = 0;
 
 static void init_tables(void) {
     if (tables_ready) return;
-    const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    const real w1[3] = {RC(1.0) / RC(6.0), RC(2.0) / RC(3.0), RC(1.0) / RC(6.0)};
     for (int cz = -1; cz <= 1; ++cz)
         for (int cy = -1; cy <= 1; ++cy)
             for (int cx = -1; cx <= 1; ++cx) {
@@ -73,12 +86,12 @@ static void init_tables(void) {
 }
 
 /* Product-form full-expansion equilibrium for one direction. */
-static double feq_dir(int a, double rho, const double u[3]) {
-    double r = rho;
+static real feq_dir(int a, real rho, const real u[3]) {
+    real r = rho;
     for (int d = 0; d < 3; ++d) {
-        double v = u[d];
+        real v = u[d];
         int c = CXYZ[a][d];
-        r *= (c == 0) ? (2.0 / 3.0 - v * v) : (1.0 / 3.0 + v * v + c * v) * 0.5;
+        r *= (c == 0) ? (RC(2.0) / RC(3.0) - v * v) : (RC(1.0) / RC(3.0) + v * v + c * v) * 0.5;
     }
     return r;
 }
@@ -108,32 +121,32 @@ static double inlet_speed(const o2_case* c, double r, double t) {
 }
 
 /* 1-D forward transform of the triple (fm, f0, fp) at c = -1, 0, +1. */
-static inline void fwd1(double* a, double* b, double* c, double u) {
-    double fm = *a, f0 = *b, fp = *c;
-    double m0 = fm + f0 + fp, d = fp - fm;
+static inline void fwd1(real* a, real* b, real* c, real u) {
+    real fm = *a, f0 = *b, fp = *c;
+    real m0 = fm + f0 + fp, d = fp - fm;
     *a = m0;
     *b = d - u * m0;
-    *c = (fp + fm) - 2.0 * u * d + (u * u - 1.0 / 3.0) * m0;
+    *c = (fp + fm) - 2.0 * u * d + (u * u - RC(1.0) / RC(3.0)) * m0;
 }
 
-static inline void inv1(double* a, double* b, double* c, double u) {
-    double m0 = *a, m1 = *b, m2 = *c;
-    double r1 = m1 + u * m0;
-    double r2 = m2 + 2.0 * u * m1 + (u * u + 1.0 / 3.0) * m0;
+static inline void inv1(real* a, real* b, real* c, real u) {
+    real m0 = *a, m1 = *b, m2 = *c;
+    real r1 = m1 + u * m0;
+    real r2 = m2 + 2.0 * u * m1 + (u * u + RC(1.0) / RC(3.0)) * m0;
     *a = 0.5 * (r2 - r1);
     *b = m0 - r2;
     *c = 0.5 * (r2 + r1);
 }
 
-static void collide_node(const o2_case* c, const double* f, double* fp, double* uo, const double g[3]) {
-    double rho = 0, j[3] = {0, 0, 0};
+static void collide_node(const o2_case* c, const real* f, real* fp, real* uo, const real g[3]) {
+    real rho = 0, j[3] = {0, 0, 0};
     for (int a = 0; a < 27; ++a) {
         rho += f[a];
         for (int d = 0; d < 3; ++d) j[d] += CXYZ[a][d] * f[a];
     }
-    double u[3];
+    real u[3];
     for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * rho * g[d]) / rho;
-    double m[27];
+    real m[27];
     memcpy(m, f, sizeof m);
     for (int q = 0; q < 9; ++q) fwd1(&m[3 * q], &m[3 * q + 1], &m[3 * q + 2], u[0]);
     for (int kz = 0; kz < 3; ++kz)
@@ -148,7 +161,7 @@ static void collide_node(const o2_case* c, const double* f, double* fp, double* 
                 int idx = 9 * k + 3 * jj + i, n = i + jj + k;
                 if (n == 0) m[idx] = rho;
                 else if (n == 1) m[idx] = 0.5 * rho * g[i == 1 ? 0 : (jj == 1 ? 1 : 2)];
-                else m[idx] *= (1.0 - c->s[n - 2]);
+                else m[idx] *= (RC(1.0) - (real)c->s[n - 2]);
             }
     for (int q = 0; q < 9; ++q) inv1(&m[q], &m[q + 9], &m[q + 18], u[2]);
     for (int kz = 0; kz < 3; ++kz)
@@ -166,40 +179,40 @@ static void collide_node(const o2_case* c, const double* f, double* fp, double* 
  *   feq2_a = w_a rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
  * plus Guo's force populations (1 - 1/(2 tau)) w_a rho [3 (c - u).g + 9 (c.u)(c.g)];
  * u = (j + rho g / 2) / rho as for CHM-MRT. */
-static void collide_node_srt2(const o2_case* c, const double* f, double* fp, double* uo, const double g[3]) {
-    double rho = 0, j[3] = {0, 0, 0};
+static void collide_node_srt2(const o2_case* c, const real* f, real* fp, real* uo, const real g[3]) {
+    real rho = 0, j[3] = {0, 0, 0};
     for (int a = 0; a < 27; ++a) {
         rho += f[a];
         for (int d = 0; d < 3; ++d) j[d] += CXYZ[a][d] * f[a];
     }
-    double u[3];
+    real u[3];
     for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * rho * g[d]) / rho;
-    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const double ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
-    const double om = 1.0 / c->tau;
+    const real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const real ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+    const real om = RC(1.0) / (real)c->tau;
     for (int a = 0; a < 27; ++a) {
-        double cu = 0, cg = 0;
+        real cu = 0, cg = 0;
         for (int d = 0; d < 3; ++d) {
             cu += CXYZ[a][d] * u[d];
             cg += CXYZ[a][d] * g[d];
         }
-        const double feq = WGT[a] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        const double F = WGT[a] * rho * (3.0 * (cg - ug) + 9.0 * cu * cg);
+        const real feq = WGT[a] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const real F = WGT[a] * rho * (3.0 * (cg - ug) + 9.0 * cu * cg);
         fp[a] = f[a] - om * (f[a] - feq) + (1.0 - 0.5 * om) * F;
     }
     for (int d = 0; d < 3; ++d) uo[d] = u[d];
 }
 
-static void g_at(const o2_case* c, int64_t t, double g[3]) {
-    double cs = cos(c->omega_g * (double)t);
+static void g_at(const o2_case* c, int64_t t, real g[3]) {
+    real cs = cos(c->omega_g * (double)t);
     for (int d = 0; d < 3; ++d) g[d] = c->g0[d] + c->g1[d] * cs;
 }
 
 /* Collide every fluid node: f -> fpost, u. */
-int o2_collide(const o2_case* c, int64_t n, const double* f, double* fpost, double* u,
+int o2_collide(const o2_case* c, int64_t n, const real* f, real* fpost, real* u,
                int64_t t, int nthreads) {
     init_tables();
-    double g[3];
+    real g[3];
     g_at(c, t, g);
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
@@ -214,22 +227,22 @@ int o2_collide(const o2_case* c, int64_t n, const double* f, double* fpost, doub
  * coords: [n][3] (x, y, z) of each node; idx: dense map cell -> node or -1.
  * mon_out[5]: wall force (3), inlet flux, outlet flux. */
 int o2_stream(const o2_case* c, const uint8_t* mask, const int32_t* coords, const int32_t* idx,
-              int64_t n, const double* fpost, const double* u, double* fnew, int64_t t,
-              double* mon_out, int nthreads, const double* wq) {
+              int64_t n, const real* fpost, const real* u, real* fnew, int64_t t,
+              real* mon_out, int nthreads, const real* wq) {
     init_tables();
     const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int dims[3] = {nx, ny, nz};
     const int per[3] = {(int)(c->periodic & 1), (int)((c->periodic >> 1) & 1), (int)((c->periodic >> 2) & 1)};
-    double ax[3] = {c->axis[0], c->axis[1], c->axis[2]};
-    double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    real ax[3] = {c->axis[0], c->axis[1], c->axis[2]};
+    real an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
     if (c->has_inlet) for (int d = 0; d < 3; ++d) ax[d] /= an;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     int nt = omp_get_max_threads();
-    double* part = (double*)calloc((size_t)nt * 5, sizeof(double));
+    real* part = (real*)calloc((size_t)nt * 5, sizeof(real));
     int bad = 0;
 #pragma omp parallel
     {
-        double* pm = part + 5 * omp_get_thread_num();
+        real* pm = part + 5 * omp_get_thread_num();
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             const int* p = coords + 3 * i;
@@ -246,28 +259,28 @@ int o2_stream(const o2_case* c, const uint8_t* mask, const int32_t* coords, cons
                     cell = ((size_t)q[2] * ny + q[1]) * nx + q[0];
                     kind = mask[cell];
                 }
-                double src = fpost[27 * i + a];
+                real src = fpost[27 * i + a];
                 int b = OPPD[a];
                 if (kind == 1) {
                     fnew[27 * (int64_t)idx[cell] + a] = src;
                 } else if (kind == 2) {
-                    double mid[3], dd[3], pr = 0, r2 = 0, uw[3];
+                    real mid[3], dd[3], pr = 0, r2 = 0, uw[3];
                     for (int d = 0; d < 3; ++d) { mid[d] = p[d] + 0.5 * CXYZ[a][d]; dd[d] = mid[d] - c->center[d]; pr += dd[d] * ax[d]; }
-                    for (int d = 0; d < 3; ++d) { double e = dd[d] - pr * ax[d]; r2 += e * e; }
-                    double sp = c->has_inlet ? inlet_speed(c, sqrt(r2), (double)t) : 0.0;
+                    for (int d = 0; d < 3; ++d) { real e = dd[d] - pr * ax[d]; r2 += e * e; }
+                    real sp = c->has_inlet ? inlet_speed(c, sqrt(r2), (real)t) : 0.0;
                     if (!c->has_inlet) bad = 1;
                     for (int d = 0; d < 3; ++d) uw[d] = sp * ax[d];
-                    double v = src + feq_dir(b, 1.0, uw) - feq_dir(a, 1.0, uw);
+                    real v = src + feq_dir(b, 1.0, uw) - feq_dir(a, 1.0, uw);
                     fnew[27 * i + b] = v;
                     pm[3] += v - src;
                 } else if (kind == 3) {
-                    const double* ux = u + 3 * i;
-                    double v = -src + feq_dir(b, c->rho_out, ux) + feq_dir(a, c->rho_out, ux);
+                    const real* ux = u + 3 * i;
+                    real v = -src + feq_dir(b, c->rho_out, ux) + feq_dir(a, c->rho_out, ux);
                     fnew[27 * i + b] = v;
                     pm[4] += v - src;
                 } else {
-                    double v = src;
-                    const double q = wq ? wq[27 * i + a] : 0.5;
+                    real v = src;
+                    const real q = wq ? wq[27 * i + a] : 0.5;
                     if (q >= 0.5) {
                         v = src / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fpost[27 * i + b];
                     } else {
@@ -299,12 +312,12 @@ int o2_stream(const o2_case* c, const uint8_t* mask, const int32_t* coords, cons
 }
 
 /* Mass and momentum of a population array: out[4]. */
-void o2_mass_momentum(int64_t n, const double* f, double* out) {
+void o2_mass_momentum(int64_t n, const real* f, real* out) {
     init_tables();
-    double m = 0, p[3] = {0, 0, 0};
+    real m = 0, p[3] = {0, 0, 0};
     for (int64_t i = 0; i < n; ++i)
         for (int a = 0; a < 27; ++a) {
-            double v = f[27 * i + a];
+            real v = f[27 * i + a];
             m += v;
             for (int d = 0; d < 3; ++d) p[d] += CXYZ[a][d] * v;
         }
@@ -316,19 +329,19 @@ void o2_mass_momentum(int64_t n, const double* f, double* out) {
  * post-collision populations and velocities.  mon[10] = mass, momentum (3),
  * wall force (3), inlet flux, outlet flux, time of the returned state. */
 int o2_run(const o2_case* c, const uint8_t* mask, const int32_t* coords, const int32_t* idx,
-           int64_t n, double* f, double* fpost, double* u, int64_t t0, int nsteps,
-           double* mon, int nthreads, const double* wq) {
+           int64_t n, real* f, real* fpost, real* u, int64_t t0, int nsteps,
+           real* mon, int nthreads, const real* wq) {
     int rc = 0;
-    double m5[5] = {0, 0, 0, 0, 0};
+    real m5[5] = {0, 0, 0, 0, 0};
     for (int s = 0; s < nsteps; ++s) {
         int64_t t = t0 + s;
         o2_collide(c, n, f, fpost, u, t, nthreads);
         rc |= o2_stream(c, mask, coords, idx, n, fpost, u, f, t, m5, nthreads, wq);
     }
-    double mm[4];
+    real mm[4];
     o2_mass_momentum(n, f, mm);
     mon[0] = mm[0]; mon[1] = mm[1]; mon[2] = mm[2]; mon[3] = mm[3];
     for (int d = 0; d < 5; ++d) mon[4 + d] = m5[d];
-    mon[9] = (double)(t0 + nsteps);
+    mon[9] = (real)(t0 + nsteps);
     return rc;
 }

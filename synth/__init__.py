@@ -14,6 +14,6 @@ from .geometry import (  # noqa: F401
     SOLID, FLUID, INLET, OUTLET,
     PERIODIC_X, PERIODIC_Y, PERIODIC_Z,
     Case, pipe_case, aneurysm_case, batch_cases, fluid_count,
-    random_tiny_case, periodic_box_case, channel_case,
+    random_tiny_case, periodic_box_case, channel_case, open_pipe_case,
 )
 from .walls import wall_links, fluid_predicate, wall_distances, random_wall_distances  # noqa: F401

@@ -105,6 +105,29 @@ def pipe_case(nx: int = 64, ny: int = 24, nz: int = 24, radius: float = 10.0,
                 meta=dict(radius=radius, center=center))
 
 
+def open_pipe_case(nx: int = 48, ny: int = 14, nz: int = 14, radius: float = 5.0,
+                   center: tuple = (6.5, 6.5), u_max: float = 0.01, tau: float = 0.8,
+                   rho_out: float = 1.0) -> Case:
+    """Straight circular pipe along x with a velocity inlet and a pressure
+    outlet: the cells inside the radius on the x = 0 layer are inlet ghosts,
+    on the x = nx - 1 layer outlet ghosts, the layers between are fluid and no
+    axis is periodic.  The inlet carries the steady Poiseuille profile of
+    centreline speed u_max (Womersley parameters with omega = 0)."""
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    z = np.arange(nz, dtype=np.float64)[None, :]
+    inside = ((y - center[0]) ** 2 + (z - center[1]) ** 2 < radius * radius).T   # [nz, ny]
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, :, 1:nx - 1] = np.where(inside[:, :, None], FLUID, SOLID)
+    mask[:, :, 0] = np.where(inside, INLET, SOLID)
+    mask[:, :, nx - 1] = np.where(inside, OUTLET, SOLID)
+    nu = (tau - 0.5) / 3.0
+    G0 = 4.0 * nu * u_max / (radius * radius)
+    inlet = Inlet(axis=(1.0, 0.0, 0.0), center=(0.0, center[0], center[1]), radius=radius,
+                  G0=G0, G1=0.0, omega=0.0)
+    return Case(name=f"openpipe{nx}x{ny}x{nz}_R{radius:g}", mask=mask, periodic=0, tau=tau,
+                rho_out=rho_out, inlet=inlet, meta=dict(radius=radius, center=center, u_max=u_max))
+
+
 def periodic_box_case(nx: int, ny: int, nz: int, tau: float = 0.8, g=(0.0, 0.0, 0.0),
                       rates=(1.0, 1.0, 1.0, 1.0)) -> Case:
     """Fully periodic box with every node fluid."""

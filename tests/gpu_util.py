@@ -30,18 +30,23 @@ def gpu_run(case, storage, steps, device="cuda:0", wall_q=None):
     return dom, f[perm]
 
 
-def oracle_post(case, steps, nthreads=16, wall_q=None):
+def oracle_post(case, steps, nthreads=16, wall_q=None, long_double=False):
     """Oracle tier O2: shifted post-collision populations f*(steps) - w and u(steps).
-    wall_q: optional (links [m, 4], q [m]) for curved walls."""
+    wall_q: optional (links [m, 4], q [m]) for curved walls.  long_double: run
+    the long-double build of the same oracle (its double build holds unshifted
+    populations of about 0.3, whose rounding reaches 1e-12 of the velocity of
+    the config-1 pipe in 2000 steps); results are returned as FP64."""
     from oracle import o2
     wq = None if wall_q is None else {tuple(int(v) for v in lk): float(q)
                                       for lk, q in zip(wall_q[0], wall_q[1])}
-    sim = o2.O2Sim(case, nthreads=nthreads, wall_q=wq)
+    sim = o2.O2Sim(case, nthreads=nthreads, wall_q=wq, long_double=long_double)
     if steps:
         sim.run(steps)
     rho, u = sim.macroscopic()
     sim.collide()
-    return sim, sim.fpost - W[None, :], rho, u
+    w = o2._weights(sim.real)
+    fhat = np.asarray(sim.fpost - w[None, :], np.float64)
+    return sim, fhat, np.asarray(rho, np.float64), np.asarray(u, np.float64)
 
 
 def moments_from_post(fhat, g):

@@ -48,15 +48,15 @@ def test_tiny_random_case_reduced_storage(storage):
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_pipe_poiseuille_2000_steps(storage, tol):
-    """The config-1 pipe driven at g = 1e-5 (u_max 2.5e-3): the oracle relaxes
-    unshifted populations (about 0.3), so each f - f_eq2 costs it about 1e-17
-    per population and step; at u_max 2.5e-4 that alone reaches 1e-12 of the
-    velocity in 2000 steps."""
+    """The config-1 pipe (g = 1e-6, u_max 2.5e-4) against the long-double
+    build of the oracle: its double build relaxes unshifted populations
+    (about 0.3), and that rounding alone reaches 2.6e-12 of the velocity in
+    2000 steps (measured against the long-double build)."""
     print(f"case srt pipe {storage}", flush=True)
-    case = _srt(synth.pipe_case(g=1e-5))
+    case = _srt(synth.pipe_case())
     dom, f = gpu_run(case, storage, 2000)
     dom.close()
-    _, _, rho_ref, u_ref = oracle_post(case, 2000)
+    _, _, rho_ref, u_ref = oracle_post(case, 2000, long_double=True)
     rho, u = moments_from_post(f, case.g)
     assert eps_u(u, u_ref) < tol
     assert np.max(np.abs(rho - rho_ref)) < tol

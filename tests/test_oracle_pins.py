@@ -576,3 +576,236 @@ def test_P12_free_third_order_rate_fixes_the_wall_position(o2lib):
         s3 = 1.0 / (0.5 + 0.1875 / (tau - 0.5))
         assert _channel_error(o2lib, tau, s3) < 1e-9
         assert _channel_error(o2lib, tau, 1.0) > 5e-4
+
+
+# ---------------------------------------------------------------------------
+# Open boundaries (Sec. 2.1.2: the bounce-back family enforces velocity and
+# pressure conditions; Sec. 2.2.1: constant inflow, open outflow) and the wall
+# force.  Readings C8 (moving-wall bounce-back), C9 (anti-bounce-back) and the
+# momentum-exchange wall force, pinned against their textbook forms and against
+# a steady open pipe.
+# ---------------------------------------------------------------------------
+
+def _one_node_case(kind, rho_out=1.0, u_max=0.05):
+    """One fluid node at (1, 1, 1) of a 3^3 box whose x = 0 face is made of
+    ghost cells of the given kind (inlet: steady Poiseuille profile along +x
+    with its axis through (y, z) = (1, 1), radius 10)."""
+    mask = np.zeros((3, 3, 3), np.uint8)
+    mask[1, 1, 1] = synth.FLUID
+    mask[:, :, 0] = kind
+    R, tau = 10.0, 0.8
+    nu = (tau - 0.5) / 3.0
+    inlet = synth.geometry.Inlet(axis=(1.0, 0.0, 0.0), center=(0.0, 1.0, 1.0), radius=R,
+                                 G0=4.0 * nu * u_max / (R * R), G1=0.0, omega=0.0)
+    return synth.Case(name=f"onenode{kind}", mask=mask, tau=tau, rho_out=rho_out, inlet=inlet), R, nu
+
+
+def _boundary_step(tier, case, fpost, u, o2lib=None):
+    """Populations arriving at the single node after streaming fpost [27]."""
+    if tier == "o1":
+        st = o1.O1State(case)
+        new, _, _, _ = o1.stream(st, fpost[None, :], u[None, :])
+        return new[1, 1, 1]
+    sim = o2lib.O2Sim(case, nthreads=1)
+    sim.stream_from_post(fpost[None, :], u[None, :], 0)
+    return sim.f[0]
+
+
+def _inlet_rule_error(tier, o2lib=None):
+    """Largest deviation of the inlet rule from Ladd's moving-wall bounce-back,
+    f_abar(x, t+1) = f*_a(x, t) - 2 w_a rho0 (c_a . u_w) / cs^2 for the link in
+    direction a into the wall, u_w the Poiseuille velocity at the link midpoint.
+    For u_w along a lattice axis the full-expansion equilibria give exactly
+    this (their difference has no higher-order terms), so the pin is sharp."""
+    case, R, nu = _one_node_case(synth.INLET)
+    rng = np.random.default_rng(3)
+    fpost = o1.W * (1.0 + rng.uniform(-0.1, 0.1, 27))
+    new = _boundary_step(tier, case, fpost, np.zeros(3), o2lib)
+    err = 0.0
+    for a in range(27):
+        c = o1.C[a]
+        if c[0] != -1:
+            continue
+        r = 0.5 * math.hypot(c[1], c[2])              # midpoint (0.5, 1 + cy/2, 1 + cz/2) from the axis
+        U = case.inlet.G0 * (R * R - r * r) / (4.0 * nu)
+        ladd = fpost[a] - 2.0 * o1.W[a] * 1.0 * (c[0] * U) / o1.CS2
+        err = max(err, abs(new[o1.OPP[a]] - ladd))
+    return err
+
+
+def _outlet_rule_error(tier, o2lib=None):
+    """Largest deviation of the outlet rule from the anti-bounce-back pressure
+    condition with the second-order equilibrium's even part,
+    f_abar(x, t+1) = -f*_a(x, t) + 2 w_a rho_out [1 + (c.u)^2 / (2 cs^4) - u.u / (2 cs^2)],
+    u the node's own velocity.  The full expansion adds terms of order u^4;
+    at |u| ~ 3e-4 they are below 1e-14."""
+    rho_out = 0.993
+    case, _, _ = _one_node_case(synth.OUTLET, rho_out=rho_out)
+    rng = np.random.default_rng(4)
+    fpost = o1.W * (1.0 + rng.uniform(-0.1, 0.1, 27))
+    u = rng.uniform(-3e-4, 3e-4, 3)
+    new = _boundary_step(tier, case, fpost, u, o2lib)
+    err = 0.0
+    for a in range(27):
+        c = o1.C[a]
+        if c[0] != -1:
+            continue
+        cu = float(c @ u)
+        abb = -fpost[a] + 2.0 * o1.W[a] * rho_out * (1.0 + cu * cu / (2 * o1.CS2 ** 2) - (u @ u) / (2 * o1.CS2))
+        err = max(err, abs(new[o1.OPP[a]] - abb))
+    return err
+
+
+INLET_RULE_TOL = 1e-14
+OUTLET_RULE_TOL = 1e-13
+
+
+@pytest.mark.parametrize("tier", ["o1", "o2"])
+def test_P21_inlet_rule_is_moving_wall_bounce_back(o2lib, tier):
+    assert _inlet_rule_error(tier, o2lib) < INLET_RULE_TOL
+
+
+@pytest.mark.parametrize("tier", ["o1", "o2"])
+def test_P22_outlet_rule_is_anti_bounce_back(o2lib, tier):
+    assert _outlet_rule_error(tier, o2lib) < OUTLET_RULE_TOL
+
+
+def test_P23_open_pipe_velocity_inlet_pressure_outlet(o2lib):
+    """Straight pipe (R = 5, 30 fluid layers, tau = 1) with the steady
+    Poiseuille profile (centreline 0.01) imposed by the inlet and rho_out = 1
+    at the outlet, run to steady state (6000 steps; the velocity then changes
+    by under 1e-6 of the centreline speed per 500 steps).  Closed forms it must meet:
+    * mass conservation: the exact flux through every plane between two
+      layers (fluid-to-fluid links only) equals the inlet inflow and the
+      outlet outflow, and is positive (flow along +x);
+    * that flux is the lattice integral of the imposed profile, sum over a
+      cross-section of u(r), within 3 % (the diagonal links sample u at
+      half-cell offsets);
+    * the developed profile is Poiseuille's, u(r) = G0 (R^2 - r^2) / (4 nu),
+      within 8 % in L2 (staircase wall of radius 5);
+    * the pressure p = rho / 3 falls linearly with Poiseuille's gradient,
+      d rho / dx = -3 G0, within 5 %;
+    * extrapolated to the outlet plane (x = nx - 3/2, midway to the ghost
+      layer) the density is rho_out within 5 % of the total drop.
+    A sign error in either boundary rule reverses the flow or lets the mass
+    run away; a dropped inlet term stops the flow."""
+    nx = 32
+    case = synth.open_pipe_case(nx=nx, tau=1.0)
+    sim = o2lib.O2Sim(case, nthreads=8)
+    sim.run(5500)
+    _, u_prev = sim.macroscopic()
+    mon = sim.run(500)
+    rho, u = sim.macroscopic()
+    assert np.max(np.abs(u - u_prev)) < 1e-6 * case.meta["u_max"]
+    x, y, z = sim.coords[:, 0], sim.coords[:, 1], sim.coords[:, 2]
+    C = o1.C
+    fp = sim.fpost
+    Q = []
+    for xx in range(1, nx - 2):
+        tot = 0.0
+        for a in range(27):
+            cx, cy, cz = C[a]
+            if cx == 0:
+                continue
+            src = x == (xx if cx == 1 else xx + 1)
+            fl = case.mask[z[src] + cz, y[src] + cy, x[src] + cx] == synth.FLUID
+            tot += cx * fp[src][fl, a].sum()
+        Q.append(tot)
+    Q = np.array(Q)
+    q_in, q_out = mon[7], mon[8]
+    assert q_in > 0
+    assert np.max(np.abs(Q - q_in)) < 1e-7 * q_in
+    assert abs(q_out + q_in) < 1e-7 * q_in
+    R = case.meta["radius"]
+    cy0, cz0 = case.meta["center"]
+    nu = case.nu
+    G0 = case.inlet.G0
+    r = np.sqrt((y - cy0) ** 2 + (z - cz0) ** 2)
+    U = G0 * (R * R - r * r) / (4.0 * nu)
+    mid = x == nx // 2
+    assert abs(q_in / U[mid].sum() - 1.0) < 0.03
+    assert np.sqrt(((u[mid, 0] - U[mid]) ** 2).sum() / (U[mid] ** 2).sum()) < 0.08
+    assert np.max(np.abs(u[mid, 1:])) < 1e-3 * case.meta["u_max"]
+    xs = np.arange(1, nx - 1)
+    rm = np.array([rho[x == xx].mean() for xx in xs])
+    sel = (xs > 5) & (xs < nx - 6)
+    slope, icept = np.polyfit(xs[sel], rm[sel], 1)
+    assert abs(slope / (-3.0 * G0) - 1.0) < 0.05
+    drop = -slope * (nx - 2)
+    assert abs(slope * (nx - 1.5) + icept - case.rho_out) < 0.05 * drop
+
+
+def _momentum_balance(case, steps, step_fn):
+    """Largest |P(t+1) - P(t) - M(t) g + F_wall(t)| over the steps, relative
+    to |M g|: each collision adds rho g per node (Sec. 2.1.1 forcing,
+    reading C6) and each halfway bounce-back link hands 2 f* c to the wall, so
+    with the momentum-exchange wall force this balance is exact to rounding."""
+    g = np.asarray(case.g, np.float64)
+    worst = 0.0
+    mass, mom = step_fn(0)
+    for k in range(steps):
+        mon = step_fn(1)
+        resid = mon[1:4] - mom - mass * g + mon[4:7]
+        worst = max(worst, float(np.max(np.abs(resid)) / np.max(np.abs(mass * g))))
+        mass, mom = mon[0], mon[1:4]
+    return worst
+
+
+def _o2_stepper(sim):
+    def fn(n):
+        if n == 0:
+            return sim.f.sum(), (sim.f @ o1.C.astype(np.float64)).sum(axis=0)
+        return sim.run(n).copy()
+    return fn
+
+
+def _o1_stepper(st):
+    def fn(n):
+        if n == 0:
+            fl = st.fluid
+            f = st.f[fl[:, 0], fl[:, 1], fl[:, 2]]
+            return f.sum(), (f @ o1.C.astype(np.float64)).sum(axis=0)
+        o1.step(st)
+        return st.monitors.copy()
+    return fn
+
+
+MOMENTUM_TOL = 1e-9
+
+
+def test_P24_wall_force_balances_momentum(o2lib):
+    """Periodic pipe under a body force (config 1 at a smaller radius): the
+    per-step momentum balance P(t+1) = P(t) + M g - F_wall holds to rounding in
+    both tiers, and at steady state the walls carry the whole driving force,
+    F_wall = M g (the transient decays as exp(-5.78 nu t / R^2), below 1e-10 of
+    it after 1200 steps at R = 5, nu = 0.1)."""
+    case = synth.pipe_case(nx=4, ny=14, nz=14, radius=5.0, center=(6.3, 6.6), g=1e-5)
+    sim = o2lib.O2Sim(case, nthreads=2)
+    assert _momentum_balance(case, 30, _o2_stepper(sim)) < MOMENTUM_TOL
+    mon = sim.run(1200)
+    Mg = mon[0] * case.g[0]
+    assert abs(mon[4] - Mg) < 1e-8 * Mg
+    assert max(abs(mon[5]), abs(mon[6])) < 1e-8 * Mg
+    small = synth.pipe_case(nx=3, ny=8, nz=8, radius=3.0, center=(3.4, 3.7), g=1e-5)
+    assert _momentum_balance(small, 4, _o1_stepper(o1.O1State(small))) < MOMENTUM_TOL
+
+
+def test_oracle_catches_planted_boundary_mistakes(o2lib, monkeypatch):
+    """A sign flip planted in the inlet rule or the outlet rule, or a wall
+    force without its factor 2 (each planted in tier O1, on the CPU), fails
+    the pin of that rule by far more than its tolerance."""
+    assert _inlet_rule_error("o1") < INLET_RULE_TOL
+    monkeypatch.setattr(o1, "moving_wall_value", lambda src, fa, fb: src - (fb - fa))
+    assert _inlet_rule_error("o1") > 1e3 * INLET_RULE_TOL
+    monkeypatch.undo()
+    assert _outlet_rule_error("o1") < OUTLET_RULE_TOL
+    monkeypatch.setattr(o1, "anti_bounce_back_value", lambda src, fa, fb: src + fb + fa)
+    assert _outlet_rule_error("o1") > 1e3 * OUTLET_RULE_TOL
+    monkeypatch.setattr(o1, "anti_bounce_back_value", lambda src, fa, fb: -src - (fb + fa))
+    assert _outlet_rule_error("o1") > 1e3 * OUTLET_RULE_TOL
+    monkeypatch.undo()
+    small = synth.pipe_case(nx=3, ny=8, nz=8, radius=3.0, center=(3.4, 3.7), g=1e-5)
+    monkeypatch.setattr(o1, "wall_force_of_links", lambda src, c: 1.0 * src.sum() * c)
+    assert _momentum_balance(small, 3, _o1_stepper(o1.O1State(small))) > 1e3 * MOMENTUM_TOL
+    monkeypatch.setattr(o1, "wall_force_of_links", lambda src, c: -2.0 * src.sum() * c)
+    assert _momentum_balance(small, 3, _o1_stepper(o1.O1State(small))) > 1e3 * MOMENTUM_TOL
