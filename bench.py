@@ -20,7 +20,6 @@ velocity error against the FP64 fine run beside the trilinear upsampling.
 
 import argparse
 import dataclasses
-import hashlib
 import json
 import math
 import os
@@ -36,11 +35,8 @@ STEP_KERNEL = "k_step"
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2101_11107_amd.profsum import kernel_source_hash as h
+    return h()
 
 
 def read_profile(storage, workload):

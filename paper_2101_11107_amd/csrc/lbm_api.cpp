@@ -246,10 +246,10 @@ namespace {
 
 // Launch nsteps steps; the last one accumulates the monitors.
 int launch_steps_eager(lbm_domain* d, int nsteps) {
+    const bool big = 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES;
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
-        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(),
-                                 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES, d->collision == 1};
+        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(), big, d->collision == 1};
         if (!d->pre.empty())
             HIP_TRY(lbm::launch_curved_pre(d->storage, const_cast<void*>(a.fin),
                                            (const lbm::CurvedLink*)(d->dev + d->off_pre), (int64_t)d->pre.size(),
@@ -555,25 +555,25 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->pop_bytes = (size_t)27 * npad * sb;
         for (size_t k = 0; k < d->spec.size(); ++k)
             for (int a = 0; a < 27; ++a) {
-                const uint64_t byte = ((uint64_t)d->spec_plane[27 * k + a] * (uint64_t)npad + d->spec[k].off[a]) * sb;
+                const uint64_t byte = (uint64_t)lbm::pop_index(d->spec[k].off[a], (uint32_t)d->spec_plane[27 * k + a], (uint32_t)npad, (uint32_t)sb) * sb;
                 d->spec[k].off[a] = (uint32_t)byte;
             }
         d->spec_plane.clear();
         d->spec_plane.shrink_to_fit();
         for (size_t k = 0; k < d->pre.size(); ++k) {
             lbm::CurvedLink& cl = d->pre[k];
-            cl.dst = (uint32_t)(((uint64_t)(26 - cl.dir) * (uint64_t)npad + cl.dst) * sb);
-            cl.src2 = (uint32_t)(((uint64_t)d->pre_src_plane[k] * (uint64_t)npad + cl.src2) * sb);
+            cl.dst = (uint32_t)((uint64_t)lbm::pop_index(cl.dst, (uint32_t)(26 - cl.dir), (uint32_t)npad, (uint32_t)sb) * sb);
+            cl.src2 = (uint32_t)((uint64_t)lbm::pop_index(cl.src2, (uint32_t)d->pre_src_plane[k], (uint32_t)npad, (uint32_t)sb) * sb);
         }
         d->pre_src_plane.clear();
         d->pre_src_plane.shrink_to_fit();
-        // plane by plane, node order inside a plane: neighbouring threads then
-        // touch neighbouring populations (the links are independent)
+        // in address order: neighbouring threads then touch neighbouring
+        // populations (the links are independent)
         std::sort(d->pre.begin(), d->pre.end(),
                   [](const lbm::CurvedLink& p, const lbm::CurvedLink& q) { return p.dst < q.dst; });
         d->pre_blocks = (int)((d->pre.size() + lbm::BLOCK - 1) / lbm::BLOCK);
         for (size_t k = 0; k < d->link_off2.size(); ++k)
-            d->link_off2[k] = (uint32_t)(((uint64_t)d->link_off2_plane[k] * (uint64_t)npad + d->link_off2[k]) * sb);
+            d->link_off2[k] = (uint32_t)((uint64_t)lbm::pop_index(d->link_off2[k], (uint32_t)d->link_off2_plane[k], (uint32_t)npad, (uint32_t)sb) * sb);
         d->link_off2_plane.clear();
         d->link_off2_plane.shrink_to_fit();
         d->off_popA = take(d->pop_bytes);

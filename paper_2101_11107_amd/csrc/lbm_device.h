@@ -3,8 +3,10 @@
 //
 // One fused pull-scheme update per fluid node (Eq. (1)): gather the 27
 // incoming post-collision populations of the previous step from the
-// structure-of-arrays buffer (halfway bounce-back for wall links, Eq. (9) at
-// q = 1/2; inlet/outlet rules for open links), form rho and j (Eqs. (4)-(5)),
+// population buffer (pop_index layout: 256-byte runs of one direction, or one
+// plane per direction for 2-byte storage; halfway bounce-back for wall links,
+// Eq. (9) at q = 1/2; inlet/outlet rules for open links), form rho and j
+// (Eqs. (4)-(5)),
 // apply the central Hermite moment collision (Eq. (6) with the equilibrium
 // central moments (rho, 0, ..., 0) of Eq. (8)) in registers with
 // one-dimensional transforms along x, y and z, and store the 27
@@ -285,8 +287,6 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
                                             uint32_t w, typename Traits<S>::T (&f)[27],
                                             uint32_t& wallmask) {
     constexpr uint32_t SZ = sizeof(S);
-    const uint32_t plane = (uint32_t)a.npad * SZ;
-    const uint32_t ib = (uint32_t)i * SZ;
     const LBM_GLOBAL char* rt = (const LBM_GLOBAL char*)a.rowtab;
     const int x = (int)(w & 1023u);
     int y = 0, z = 0;
@@ -328,13 +328,13 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
             const int al = 9 * kz + 3 * ky + kx;
             const int k = 2 - kx;              // bit of the source cell x - cx
             if (al == 13) {
-                f[al] = ldp<S>(fin, 13u * plane + ib);
+                f[al] = ldp<S>(fin, pop_index((uint32_t)i, 13u, (uint32_t)a.npad, SZ) * SZ);
                 continue;
             }
             const bool fl = (win >> k) & 1u;
             const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
-            const uint32_t off = fl ? (uint32_t)al * plane + (uint32_t)src * SZ
-                                    : (uint32_t)(26 - al) * plane + ib;
+            const uint32_t off = fl ? pop_index((uint32_t)src, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ
+                                    : pop_index((uint32_t)i, (uint32_t)(26 - al), (uint32_t)a.npad, SZ) * SZ;
             f[al] = ldp<S>(fin, off);
             if (WALLS && !fl) wallmask |= 1u << al;
         }
@@ -635,10 +635,8 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             mon[7] = qin;
             mon[8] = qout;
         }
-        const uint32_t plane = (uint32_t)a.npad * SZ;
-        const uint32_t ib = (uint32_t)i * SZ;
 #pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S, NT>(fout, (uint32_t)al * plane + ib, f[al]);
+        for (int al = 0; al < 27; ++al) stp<S, NT>(fout, pop_index((uint32_t)i, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ, f[al]);
         // after the stores, so the populations are no longer live
         if (sp != nullptr && sp->linkmask != 0u)
             update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);

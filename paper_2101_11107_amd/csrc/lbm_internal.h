@@ -19,6 +19,23 @@ constexpr int MAX_DIM = 1023;
 constexpr int BLOCK = 256;            // threads per work-group of the step kernel
 constexpr int MON_WORDS = 10;         // doubles per work-group monitor partial
 
+// Population layout.  4- and 8-byte populations are stored in tiles of
+// 256-byte runs: T = 256 / size consecutive nodes (64 in FP32, 32 in FP64)
+// form a tile that holds their 27 directions one after another, each as one
+// run of T consecutive values, so element (node i, direction a) is at
+// (i / T) 27 T + a T + i % T.  A wave's loads and stores of one direction
+// then cover whole runs, and the 27 runs of a tile are adjacent in memory.
+// 2-byte populations keep one plane per direction, element a npad + i (a
+// 64-node run of them would be a single 128-byte line; planes measured
+// faster for them).  npad is a multiple of 256, so every tile is whole.
+constexpr uint32_t POP_RUN_BYTES = 256;
+__host__ __device__ __forceinline__ constexpr uint32_t pop_tile_shift(uint32_t sz) { return sz == 8 ? 5u : 6u; }
+__host__ __device__ __forceinline__ constexpr uint32_t pop_index(uint32_t i, uint32_t a, uint32_t npad, uint32_t sz) {
+    return sz == 2 ? a * npad + i
+                   : (i >> pop_tile_shift(sz)) * (27u << pop_tile_shift(sz)) + (a << pop_tile_shift(sz)) +
+                         (i & ((1u << pop_tile_shift(sz)) - 1u));
+}
+
 // Row table entry k of a row: fluid bits of the 32 cells 30k - 1 .. 30k + 30
 // (bit j for cell 30k - 1 + j; neighbouring entries overlap by two cells, so
 // the cells x - 1, x, x + 1 of any x in 30k .. 30k + 29 sit in entry k) and the
@@ -76,7 +93,7 @@ static_assert(sizeof(CurvedLink) == 32, "curved-wall record is 32 bytes");
 // f_eq_a + f_eq_abar - 2 w_a at rho_out and the node's velocity).
 constexpr int LINK_COEFS = 6;
 struct StepArgs {
-    const void* fin;             // post-collision populations of time t  [27][npad]
+    const void* fin;             // post-collision populations of time t (pop_index layout, npad nodes)
     void* fout;                  // post-collision populations of time t+1
     const uint32_t* node;        // [npad] descriptor words
     const RowEntry* rowtab;      // [rows][W]

@@ -49,9 +49,8 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs a, const double* rho0, 
         if (sp->linkmask != 0u) update_links(a, sp, (double)ux, (double)uy, (double)uz, 0);
     }
     LBM_GLOBAL char* fout = (LBM_GLOBAL char*)a.fout;
-    const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
-    for (int al = 0; al < 27; ++al) stp<S>(fout, (uint32_t)al * plane + (uint32_t)i * SZ, f[al]);
+    for (int al = 0; al < 27; ++al) stp<S>(fout, pop_index((uint32_t)i, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ, f[al]);
 }
 
 // rho and u of the current state from the post-collision populations, in FP64:
@@ -72,11 +71,10 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, double* rho, doub
         return;
     }
     const LBM_GLOBAL char* fin = (const LBM_GLOBAL char*)a.fin;
-    const uint32_t plane = (uint32_t)a.npad * SZ;
     double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int al = 0; al < 27; ++al) {
-        const double v = (double)ldp<S>(fin, (uint32_t)al * plane + (uint32_t)i * SZ);
+        const double v = (double)ldp<S>(fin, pop_index((uint32_t)i, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ);
         d += v;
         jx += cxo(al) * v;
         jy += cyo(al) * v;
@@ -106,10 +104,9 @@ __global__ __launch_bounds__(BLOCK) void k_read_pop(StepArgs a, double* out) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const LBM_GLOBAL char* fin = (const LBM_GLOBAL char*)a.fin;
-    const uint32_t plane = (uint32_t)a.npad * SZ;
 #pragma unroll
     for (int al = 0; al < 27; ++al)
-        out[(size_t)al * a.n + i] = (double)ldp<S>(fin, (uint32_t)al * plane + (uint32_t)i * SZ);
+        out[(size_t)al * a.n + i] = (double)ldp<S>(fin, pop_index((uint32_t)i, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ);
 }
 
 // Fixed-order reduction of the per-block monitor partials (one work-group).
