@@ -142,12 +142,10 @@ def batch_bench(torch, lbm, steps, storage="f16s"):
     stepped one after another (each with its own graph replays)."""
     import synth
     cases = synth.batch_cases()
-    doms = [lbm.Domain(c, storage=storage) for c in cases]
-    for d in doms:
-        d.init()
+    # the autotuner times every execution choice of the batch for each
+    # row-tile edge of the node order and keeps the fastest
+    b, doms, tile, tuned_ms, tile_ms = lbm.autotune_batch(cases, storage, row_tiles=(4, 8, 16), trial_steps=32)
     total = sum(d.n for d in doms)
-    b = lbm.Batch(doms)
-    tuned_ms = b.autotune(trial_steps=32, want_time=True)
     cfg = b.config()
     b.step(32)
     torch.cuda.synchronize()
@@ -175,7 +173,8 @@ def batch_bench(torch, lbm, steps, storage="f16s"):
             "sequential_mlups": round(total * steps / t_seq / 1e6, 1),
             "batched_over_sequential": round(t_seq / t_batch, 3),
             "autotuned_config": {"mode": ["launch_per_step", "persistent"][cfg[0]], "block": cfg[1],
-                                 "stream_store": cfg[2], "grid": cfg[3], "group_mb": cfg[4]},
+                                 "stream_store": cfg[2], "grid": cfg[3], "group_mb": cfg[4], "row_tile": tile},
+            "autotune_best_ms_per_step_by_row_tile": {str(k): round(v, 4) for k, v in tile_ms.items()},
             "autotune_best_ms_per_step": round(tuned_ms, 4),
             "roofline_frac": roofline(total, ms, storage, None)["frac"]}
 

@@ -89,7 +89,8 @@ const char* lbm_last_error(void);
  * LBM_F64 / F32 / F16S / BF16S.  hip_stream: hipStream_t (NULL = default).
  * Fluid nodes are numbered row by row, x fastest within a row; the (y, z)
  * rows are taken in tiles of 8 x 8 (tile y fastest, then tile z, and y
- * fastest inside a tile).  lbm_fluid_coords gives the order explicitly.
+ * fastest inside a tile; lbm_create_domain_ex sets another tile edge).
+ * lbm_fluid_coords gives the order explicitly.
  * Errors: EINVAL for bad sizes, values or flags; ENOMEM on host allocation. */
 int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
                       int storage, void* hip_stream, lbm_domain** out);
@@ -116,6 +117,18 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
 int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,
                              int storage, const int32_t* links, const double* q, int64_t nwall,
                              void* hip_stream, lbm_domain** out);
+
+/* lbm_create_domain with layout options: the (y, z) rows are taken in tiles
+ * of row_tile x row_tile (1, 2, 4, 8, 16 or 32; lbm_create_domain and
+ * lbm_create_domain_curved use 8), which changes only the node order, never
+ * a result; with nwall > 0 the walls are curved as in
+ * lbm_create_domain_curved (links and q NULL with nwall 0 give halfway walls).
+ * It serves the choice of the list order by timing (batch autotuning).
+ * Errors: EINVAL for any other row_tile; otherwise as the two functions it
+ * generalizes. */
+int lbm_create_domain_ex(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                         const int32_t* links, const double* q, int64_t nwall, int row_tile, void* hip_stream,
+                         lbm_domain** out);
 
 /* Wall links of a mask (same layout and periodic rules as lbm_create_domain):
  * every pair of a FLUID cell and a direction alpha whose cell x + c_alpha is

@@ -39,7 +39,7 @@ using namespace lbm_host;
 
 namespace {
 
-constexpr int ROW_TILE = 8;   // rows per tile side in the list order
+constexpr int ROW_TILE = 8;   // default rows per tile side in the list order
 
 size_t storage_bytes(int storage) {
     switch (storage) {
@@ -309,7 +309,7 @@ namespace {
 using WallQ = std::unordered_map<int64_t, double>;
 
 int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
-                  void* hip_stream, const WallQ* wq, lbm_domain** out) {
+                  void* hip_stream, const WallQ* wq, int row_tile, lbm_domain** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!mask) return fail(LBM_EINVAL, "mask is NULL");
@@ -357,16 +357,16 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                     if (j <= 1 && k >= 1) d->rowtab[r + k - 1].bits |= 1u << (j + lbm::ROW_SPAN);
                 }
             }
-        // List order: rows grouped in tiles of ROW_TILE x ROW_TILE rows of the
+        // List order: rows grouped in tiles of row_tile x row_tile rows of the
         // (y, z) plane, x fastest inside a row.  Neighbouring rows then sit close
         // together in the list, so the lines a wave gathers from are shared by
         // waves that run at nearly the same time.
         std::vector<int> order;
         order.reserve((size_t)ny * nz);
-        for (int tz = 0; tz < nz; tz += ROW_TILE)
-            for (int ty = 0; ty < ny; ty += ROW_TILE)
-                for (int z = tz; z < std::min(nz, tz + ROW_TILE); ++z)
-                    for (int y = ty; y < std::min(ny, ty + ROW_TILE); ++y) order.push_back(d->row_of(y, z));
+        for (int tz = 0; tz < nz; tz += row_tile)
+            for (int ty = 0; ty < ny; ty += row_tile)
+                for (int z = tz; z < std::min(nz, tz + row_tile); ++z)
+                    for (int y = ty; y < std::min(ny, ty + row_tile); ++y) order.push_back(d->row_of(y, z));
         int64_t cnt = 0;
         for (int r : order) {
             const int z = r / (ny + 2) - 1, y = r % (ny + 2) - 1;
@@ -623,7 +623,7 @@ extern "C" {
 
 int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
                       void* hip_stream, lbm_domain** out) {
-    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, nullptr, out);
+    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, nullptr, ROW_TILE, out);
 }
 
 int lbm_wall_links(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int32_t* links,
@@ -654,16 +654,18 @@ int lbm_wall_links(const uint8_t* mask, int nx, int ny, int nz, unsigned periodi
     return LBM_OK;
 }
 
-int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
-                             const int32_t* links, const double* q, int64_t nwall, void* hip_stream,
-                             lbm_domain** out) {
-    if (!out) return fail(LBM_EINVAL, "out is NULL");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Validate the curved-wall links of lbm_create_domain_curved and key their
+// distances by (cell * 27 + incoming direction).
+int wall_q_from_links(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, const int32_t* links,
+                      const double* q, int64_t nwall, WallQ& wq) {
     if (!mask || nwall < 0 || (nwall > 0 && (!links || !q))) return fail(LBM_EINVAL, "NULL argument");
     if (nx < 1 || ny < 1 || nz < 1 || nx > lbm::MAX_DIM || ny > lbm::MAX_DIM || nz > lbm::MAX_DIM)
         return fail(LBM_EINVAL, "dimensions must be in [1, 1023]");
     if (periodic_bits > 7) return fail(LBM_EINVAL, "periodic_bits must be a combination of LBM_PERIODIC_*");
-    WallQ wq;
     try {
         wq.reserve((size_t)nwall);
         for (int64_t k = 0; k < nwall; ++k) {
@@ -682,7 +684,37 @@ int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsign
     } catch (const std::bad_alloc&) {
         return fail(LBM_ENOMEM, "host allocation failed");
     }
-    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, &wq, out);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                             const int32_t* links, const double* q, int64_t nwall, void* hip_stream,
+                             lbm_domain** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    WallQ wq;
+    const int rc = wall_q_from_links(mask, nx, ny, nz, periodic_bits, links, q, nwall, wq);
+    if (rc) return rc;
+    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, &wq, ROW_TILE, out);
+}
+
+int lbm_create_domain_ex(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits, int storage,
+                         const int32_t* links, const double* q, int64_t nwall, int row_tile, void* hip_stream,
+                         lbm_domain** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (row_tile < 1 || row_tile > 32 || (row_tile & (row_tile - 1)) != 0)
+        return fail(LBM_EINVAL, "row_tile must be 1, 2, 4, 8, 16 or 32");
+    if (nwall == 0 && !links && !q)
+        return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, nullptr, row_tile, out);
+    WallQ wq;
+    const int rc = wall_q_from_links(mask, nx, ny, nz, periodic_bits, links, q, nwall, wq);
+    if (rc) return rc;
+    return create_domain(mask, nx, ny, nz, periodic_bits, storage, hip_stream, &wq, row_tile, out);
 }
 
 int lbm_device_bytes(const lbm_domain* d, size_t* bytes) {

@@ -26,7 +26,7 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
 
 EXPORTED = [
-    "lbm_last_error", "lbm_create_domain", "lbm_create_domain_curved", "lbm_wall_links",
+    "lbm_last_error", "lbm_create_domain", "lbm_create_domain_curved", "lbm_create_domain_ex", "lbm_wall_links",
     "lbm_device_bytes", "lbm_attach_device",
     "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_collision", "lbm_set_inlet_womersley",
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
@@ -71,6 +71,8 @@ def load():
                                ctypes.POINTER(_P)], ctypes.c_int),
         "lbm_create_domain_curved": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int,
                                       _P, _P, ctypes.c_int64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "lbm_create_domain_ex": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int,
+                                  _P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(_P)], ctypes.c_int),
         "lbm_wall_links": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _P,
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_set_collision": ([_P, ctypes.c_int], ctypes.c_int),
@@ -177,6 +179,27 @@ def lbm_create_domain_curved(mask: np.ndarray, periodic_bits: int, storage: int,
     _check(load().lbm_create_domain_curved(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), int(storage),
                                            lk.ctypes.data_as(_P), qq.ctypes.data_as(_P), len(qq),
                                            _P(hip_stream), ctypes.byref(out)))
+    return out
+
+
+def lbm_create_domain_ex(mask: np.ndarray, periodic_bits: int, storage: int, links, q, row_tile: int,
+                         hip_stream: int):
+    """lbm_create_domain / lbm_create_domain_curved with the row-tile edge of
+    the node order; links and q may be None (halfway walls)."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = m.shape
+    if links is None:
+        lk_p = qq_p = None
+        nwall = 0
+    else:
+        lk = np.ascontiguousarray(links, np.int32).reshape(-1, 4)
+        qq = np.ascontiguousarray(q, np.float64).reshape(-1)
+        if len(lk) != len(qq):
+            raise ValueError("links and q differ in length")
+        lk_p, qq_p, nwall = lk.ctypes.data_as(_P), qq.ctypes.data_as(_P), len(qq)
+    out = _P()
+    _check(load().lbm_create_domain_ex(m.ctypes.data_as(_P), nx, ny, nz, int(periodic_bits), int(storage), lk_p,
+                                       qq_p, nwall, int(row_tile), _P(hip_stream), ctypes.byref(out)))
     return out
 
 
@@ -359,9 +382,11 @@ class Domain:
     ``g``, ``rho_out`` and ``inlet`` attributes (see the ``synth`` package).
     ``wall_q``: optional (links [m, 4], q [m]) for curved walls (interpolated
     bounce-back on those links, see ``lbm_create_domain_curved``).
+    ``row_tile``: optional row-tile edge of the node order (see
+    ``lbm_create_domain_ex``; the default order uses 8).
     """
 
-    def __init__(self, case, storage="f32", device="cuda:0", stream=None, wall_q=None):
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None, wall_q=None, row_tile=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required (the library has no CPU path)")
@@ -372,7 +397,12 @@ class Domain:
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.case = case
-        if wall_q is None:
+        if row_tile is not None:
+            self.handle = lbm_create_domain_ex(case.mask, case.periodic, self.storage,
+                                               None if wall_q is None else wall_q[0],
+                                               None if wall_q is None else wall_q[1], row_tile,
+                                               self.stream.cuda_stream)
+        elif wall_q is None:
             self.handle = lbm_create_domain(case.mask, case.periodic, self.storage, self.stream.cuda_stream)
         else:
             self.handle = lbm_create_domain_curved(case.mask, case.periodic, self.storage, wall_q[0], wall_q[1],
@@ -537,3 +567,35 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune_batch(cases, storage="f16s", row_tiles=(4, 8, 16), trial_steps=32, device="cuda:0"):
+    """The batch autotuner over node orders as well: for each row-tile edge
+    the domains are built in that order (lbm_create_domain_ex) and batched,
+    and the library's autotuner (lbm_batch_autotune) times its execution
+    choices on them; the fastest order is kept.  Returns (batch, domains,
+    row_tile, best ms per step, {row_tile: best ms per step}); the batch and
+    the domains of the other orders are closed."""
+    best = None
+    times = {}
+    for tile in row_tiles:
+        doms = [Domain(c, storage=storage, device=device, row_tile=tile) for c in cases]
+        for d in doms:
+            d.init()
+        b = Batch(doms)
+        ms = b.autotune(trial_steps=trial_steps, want_time=True)
+        times[tile] = ms
+        if best is None or ms < best[3]:
+            if best is not None:
+                _close_all(best[0], best[1])
+            best = (b, doms, tile, ms)
+        else:
+            _close_all(b, doms)
+    return best + (times,)
+
+
+def _close_all(batch, doms):
+    batch.close()
+    for d in doms:
+        d.close()
+

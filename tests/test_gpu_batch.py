@@ -1,5 +1,7 @@
-"""Batched stepping: every domain of a batch must end bit-identical to stepping
-it alone, in every execution configuration the autotuner may pick."""
+"""Batched stepping: every domain of a batch against the FP64 CPU oracle run
+on that domain's own geometry and parameters (mixed relaxation times, both
+batch modes), and bit-identical to stepping it alone in every execution
+configuration the autotuner may pick."""
 
 import numpy as np
 import pytest
@@ -54,6 +56,51 @@ def test_batch_equals_solo_bitwise(storage, cfg):
         assert np.array_equal(f, fs)
         # monitor sums may differ in order (different work-group sizes)
         assert np.max(np.abs(m - ms) / np.maximum(np.abs(ms), 1.0)) < 1e-12
+
+
+_ORACLE = {}   # oracle results per case, shared by the parametrizations
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16s", 1e-3)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_matches_oracle(storage, tol, mode):
+    """Four uneven geometries (boxes 64..128, tau between 0.51 and 1, each
+    with its own Womersley inlet) stepped 100 times together by the batch
+    kernels (mode 0: one launch per step for all domains; mode 1: one
+    persistent launch), each against oracle O2 on its own case: the shifted
+    post-collision populations element by element and the velocity error,
+    within the storage form's bound (FP32 1e-5, f16s 1e-3 of the largest
+    value)."""
+    from gpu_util import eps_u, moments_from_post, oracle_order, oracle_post
+    from paper_2101_11107_amd import lbm
+    cases = [c for c in synth.batch_cases(first_seed=2000, count=12) if c.mask.shape[0] <= 128][:4]
+    assert len(cases) == 4 and len({round(c.tau, 6) for c in cases}) == 4
+    print(f"case batch vs oracle {storage} mode {mode}: {[c.name for c in cases]}", flush=True)
+    steps = 100
+    doms = [lbm.Domain(c, storage=storage) for c in cases]
+    for d in doms:
+        d.init()
+    b = lbm.Batch(doms)
+    b.set_config((mode, 256, 0, 0, 0))
+    b.step(steps)
+    b.status()
+    got = []
+    for c, d in zip(cases, doms):
+        f = d.populations().cpu().numpy().T
+        got.append(f[oracle_order(d.coords(), c.mask)])
+    b.close()
+    for d in doms:
+        d.close()
+    for c, f in zip(cases, got):
+        if c.name not in _ORACLE:
+            _, ref, _, u_ref = oracle_post(c, steps)
+            _ORACLE[c.name] = (ref, u_ref)
+        ref, u_ref = _ORACLE[c.name]
+        err = float(np.max(np.abs(f - ref)) / np.max(np.abs(ref)))
+        _, u = moments_from_post(f, c.g)
+        print(f"  {c.name}: tau {c.tau:.4f}  population error {err:.2e}  eps_u {eps_u(u, u_ref):.2e}", flush=True)
+        assert err < tol
+        assert eps_u(u, u_ref) < tol
 
 
 def test_batch_autotune_and_continue():

@@ -33,6 +33,41 @@ def test_fluid_list_and_tile_order():
         lbm.lbm_destroy(dom)
 
 
+@pytest.mark.parametrize("tile", [1, 4, 8, 16, 32])
+def test_row_tile_option_changes_only_the_order(tile):
+    """lbm_create_domain_ex takes the (y, z) rows in tiles of the given edge:
+    the same fluid cells in another order (edge 8 is the default order), with
+    or without curved-wall links."""
+    lbm = _lbm()
+    case = synth.random_tiny_case(4, nx=20, ny=37, nz=21)
+    ref = lbm.lbm_create_domain(case.mask, case.periodic, lbm.LBM_F32, 0)
+    links = synth.wall_links(case.mask, case.periodic)
+    doms = [lbm.lbm_create_domain_ex(case.mask, case.periodic, lbm.LBM_F32, None, None, tile, 0),
+            lbm.lbm_create_domain_ex(case.mask, case.periodic, lbm.LBM_F32, links, np.full(len(links), 0.3),
+                                     tile, 0)]
+    try:
+        want = lbm.lbm_fluid_coords(ref)
+        for dom in doms:
+            xyz = lbm.lbm_fluid_coords(dom)
+            assert sorted(map(tuple, xyz)) == sorted(map(tuple, want))
+            key = [((z // tile) * 100 + (y // tile), z % tile, y % tile, x) for x, y, z in xyz]
+            assert key == sorted(key)
+            if tile == 8:
+                assert np.array_equal(xyz, want)
+    finally:
+        for d in (ref, *doms):
+            lbm.lbm_destroy(d)
+
+
+@pytest.mark.parametrize("tile", [0, 3, 64, -8])
+def test_row_tile_option_rejects_other_edges(tile):
+    lbm = _lbm()
+    case = synth.random_tiny_case(1)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_domain_ex(case.mask, case.periodic, lbm.LBM_F32, None, None, tile, 0)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
 def test_aneurysm_fluid_counts():
     lbm = _lbm()
     for n, expect in ((256, 262221),):
