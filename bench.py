@@ -375,6 +375,16 @@ def main():
                     row["mass_drift_vs_f64"] = abs(r["monitors"][0] - ref["monitors"][0]) / ref["monitors"][0]
                 also.append(row)
             del ref
+        # the 512^3 configuration over its full length (five inlet periods):
+        # every storage form against the FP64 run
+        from paper_2101_11107_amd import precision
+        case512 = case if workload == "aneurysm512" else synth.aneurysm_case(512, seed=0)
+        ps = precision.study(case512, 40000)
+        also.append({"workload": "aneurysm512_full_length_storage_forms", "steps": ps["steps"],
+                     "average_steps": ps["average_steps"],
+                     "vs_f64": {st: {k: (round(v, 10) if isinstance(v, float) else v) for k, v in ps[st].items()}
+                                for st in ("f32", "f16s", "bf16s")}})
+        note(f"precision study 40000 steps: {also[-1]['vs_f64']}")
         also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, main_run))
         note(f"curved walls: {also[-1]['mlups']:.1f} MLUPS, pipe order {also[-1]['pipe_order']}")
         # SRT comparator: its step rate on the same run, and the stability sweep

@@ -179,8 +179,9 @@ def test_network_matches_oracle_with_bf16_storage():
     """Forward, loss and all 22 parameter gradients of the whole network
     against the oracle with the same BF16 storage points.  FP32 versus FP64
     accumulation can move a stored activation by one BF16 step (2^-8
-    relative) and, rarely, flip a ReLU decision near zero; the bounds allow
-    for that and nothing more (relative L2 per tensor)."""
+    relative) and, rarely, flip a ReLU decision near zero.  Measured: output
+    1.2e-5 and loss 3e-8 relative, every gradient within 3e-3 relative L2
+    (cosine above 0.99999); the bounds are about ten times those."""
     torch = _torch()
     from paper_2101_11107_amd import net as nn
     n, d, h, w = 2, 4, 4, 32
@@ -203,8 +204,8 @@ def test_network_matches_oracle_with_bf16_storage():
 
     e_out = np.linalg.norm(out - out_ref) / np.linalg.norm(out_ref)
     print(f"  out rel L2 {e_out:.3e}  loss {loss:.8e} vs {loss_ref:.8e}", flush=True)
-    assert e_out < 2e-3
-    assert abs(loss - loss_ref) / loss_ref < 2e-3
+    assert e_out < 1.5e-4
+    assert abs(loss - loss_ref) / loss_ref < 3e-7
     for k in nn.LAYER_NAMES:
         for i, nm in ((0, "w"), (1, "b")):
             ref = g_ref[k][i]
@@ -212,7 +213,7 @@ def test_network_matches_oracle_with_bf16_storage():
             e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             cos = float((got * ref).sum() / (np.linalg.norm(got) * np.linalg.norm(ref)))
             print(f"  grad {k}.{nm}: rel L2 {e:.3e} cos {cos:.6f}", flush=True)
-            assert e < 3e-2 and cos > 0.999, (k, nm)
+            assert e < 3e-2 and cos > 0.9999, (k, nm)
     # deterministic: the same call gives the same bits
     assert loss2 == loss
     assert torch.equal(grad, grad2)
