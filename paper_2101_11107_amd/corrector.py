@@ -349,7 +349,14 @@ def main(argv=None):
     ap.add_argument("--test", type=int, default=16, help="held-out seeds after the training seeds")
     ap.add_argument("--iters", type=int, default=6000)
     ap.add_argument("--out", default=None, help="write the summary (JSON) and parameters (.npy) here")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (profile counter calibration)")
     a = ap.parse_args(argv)
+    if a.copy_probe_mib:
+        import torch
+        src = torch.empty(a.copy_probe_mib << 20, dtype=torch.uint8, device="cuda:0")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
     cfg = TrainConfig(iters=a.iters, log_every=max(1, a.iters // 10))
     res = run_protocol(range(a.train), range(a.train, a.train + a.test), cfg,
                        log=lambda m: print(m, flush=True))

@@ -498,17 +498,34 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(WgradArgs a, int nparts)
 // give all three (dx = 1 by 16-bit funnel shifts).  The four waves' sums are
 // added in LDS in a fixed order (wave 3, 2, 1, 0) before the partial is
 // written.
+//
+// LDS banks (32 of 4 bytes): the halo rows of the 16 channels sit HSTR
+// halves apart (HSTR / 2 = 2 mod 32 dwords) and the gradient rows GSTR
+// halves apart (GSTR / 2 = 4 mod 32), and lane quarter q takes row
+// y = 2 m + (q & 1), x = 8 (q >> 1): the 4-byte halo reads of 32
+// consecutive lanes (channel r16, two quarters) then touch 32 different banks,
+// and the 16-byte gradient reads spread evenly over the banks.  Both
+// transposes write whole dwords (two voxels of one channel): the halo from
+// pairs of voxels a thread loads, the gradient after a swap with the
+// neighbouring lane.
 template <int CIN>
 __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts) {
     constexpr int NHALO = HZ * HY * HX;
     constexpr int NB = BX * BY * BZ;                 // voxels per brick (256, one per thread)
-    constexpr int HITER = (NHALO * 2 + 255) / 256;   // 16-byte halo pieces per thread (8 channels each)
-    constexpr int LDS_HALFS = 16 * NHALO + 16 * NB;
+    constexpr int HSTR = 708;                        // halves per halo channel row (>= NHALO)
+    constexpr int GSTR = 264;                        // halves per gradient channel row (>= NB)
+    constexpr int NPAIR = NHALO / 2;                 // voxel pairs of one channel row
+    constexpr int HITER = (2 * NPAIR + 255) / 256;   // (pair, channel half) tasks per thread
+    constexpr int LDS_HALFS = 16 * HSTR + 16 * GSTR;
     static_assert(BZ == 4 && BX == 16 && BY == 4, "one z-slice per wave, four K-steps of 16 per slice");
+    static_assert(HX % 2 == 0 && HSTR >= NHALO && GSTR >= NB && (HSTR / 2) % 32 == 2 && (GSTR / 2) % 32 == 4,
+                  "voxel pairs stay in one halo row; row strides as the bank layout needs");
     static_assert(27 * 4 * 64 * 4 <= LDS_HALFS * 2, "the wave reduction fits in the staging space");
     __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_HALFS];
-    uint16_t* halo = lds;                 // [16 channels][NHALO]
-    uint16_t* gy = lds + 16 * NHALO;      // [16 output channels][NB]
+    uint16_t* halo = lds;                 // [16 channels][HSTR]
+    uint16_t* gy = lds + 16 * HSTR;       // [16 output channels][GSTR]
+    uint32_t* halo32 = (uint32_t*)halo;
+    uint32_t* gy32 = (uint32_t*)gy;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, r16 = lane & 15;
     const int tx = a.w / BX, ty = a.h / BY, tz = a.d / BZ;
@@ -518,12 +535,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
     const int c0 = 16 * ((int)blockIdx.y % CG);        // first input channel of this work-group
     const int co0 = 16 * ((int)blockIdx.y / CG);       // first output channel of this work-group
     const int gq = (a.cout - co0) >> 2 < 4 ? (a.cout - co0) >> 2 : 4;   // 4-channel gradient pieces
-    for (int k = threadIdx.x; k < 16 * NB; k += 256) gy[k] = 0;   // rows co >= cout stay zero
+    for (int k = threadIdx.x; k < 16 * GSTR / 2; k += 256) gy32[k] = 0u;   // rows co >= cout stay zero
     v4f acc[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    uint4 hreg[HITER];
+    uint4 hreg[HITER][2];   // channels 8 p .. 8 p + 7 of voxels 2 m and 2 m + 1
     uint2 greg[4];
     auto fetch = [&](int64_t br) {
         int64_t b = br;
@@ -537,13 +554,19 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
         const int64_t sbase = (int64_t)s * V;
 #pragma unroll
         for (int i = 0; i < HITER; ++i) {
-            const int idx = (int)threadIdx.x + 256 * i;
-            const int vox = idx >> 1, p = idx & 1;
-            const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-            const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
-            const bool in = idx < NHALO * 2 && xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 && zz < a.d;
-            const uint16_t* src = a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + c0 + 8 * p;
-            hreg[i] = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+            const int task = (int)threadIdx.x + 256 * i;
+            const int p = task >= NPAIR, m = task - p * NPAIR;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int vox = 2 * m + h;
+                const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+                const int xx = xs + hx, yy = ys + hy, zz = zs + hz;
+                const bool in = task < 2 * NPAIR && xx >= 0 && xx < a.w && yy >= 0 && yy < a.h && zz >= 0 &&
+                                zz < a.d;
+                const uint16_t* src =
+                    a.x + (sbase + ((int64_t)zz * a.h + yy) * a.w + xx) * a.ldx + a.cxo + c0 + 8 * p;
+                hreg[i][h] = in ? *(const uint4*)src : uint4{0u, 0u, 0u, 0u};
+            }
         }
         const int v = threadIdx.x;
         const int vx = v % BX, vy = (v / BX) % BY, vz = v / (BX * BY);
@@ -555,33 +578,49 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_k16(WgradArgs a, int nparts)
     auto stage = [&]() {
 #pragma unroll
         for (int i = 0; i < HITER; ++i) {
-            const int idx = (int)threadIdx.x + 256 * i;
-            if (idx >= NHALO * 2) continue;
-            const int vox = idx >> 1, p = idx & 1;
-            const uint32_t ww[4] = {hreg[i].x, hreg[i].y, hreg[i].z, hreg[i].w};
+            const int task = (int)threadIdx.x + 256 * i;
+            if (task >= 2 * NPAIR) continue;
+            const int p = task >= NPAIR, m = task - p * NPAIR;
+            const uint32_t lo[4] = {hreg[i][0].x, hreg[i][0].y, hreg[i][0].z, hreg[i][0].w};
+            const uint32_t hi[4] = {hreg[i][1].x, hreg[i][1].y, hreg[i][1].z, hreg[i][1].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                halo[(8 * p + 2 * e) * NHALO + vox] = (uint16_t)(ww[e] & 0xffffu);
-                halo[(8 * p + 2 * e + 1) * NHALO + vox] = (uint16_t)(ww[e] >> 16);
+                // channel 8 p + 2 e from the low halves, 8 p + 2 e + 1 from the high halves
+                halo32[(8 * p + 2 * e) * (HSTR / 2) + m] = (lo[e] & 0xffffu) | (hi[e] << 16);
+                halo32[(8 * p + 2 * e + 1) * (HSTR / 2) + m] = (lo[e] >> 16) | (hi[e] & 0xffff0000u);
             }
         }
+        // gradient: even lanes write channels 0..7, odd lanes 8..15, each as
+        // dwords (voxel v & ~1 in the low half, v | 1 in the high half)
         const int v = threadIdx.x;
+        const bool odd = v & 1;
+        uint32_t own[8], nb[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (k >= gq) continue;
-            gy[(4 * k + 0) * NB + v] = (uint16_t)(greg[k].x & 0xffffu);
-            gy[(4 * k + 1) * NB + v] = (uint16_t)(greg[k].x >> 16);
-            gy[(4 * k + 2) * NB + v] = (uint16_t)(greg[k].y & 0xffffu);
-            gy[(4 * k + 3) * NB + v] = (uint16_t)(greg[k].y >> 16);
+            own[2 * k] = greg[k].x;
+            own[2 * k + 1] = greg[k].y;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nb[k] = (uint32_t)__shfl_xor((int)own[k], 1, 64);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // word k (even lane) or 4 + k (odd lane) of the 8 words, two channels each
+            const uint32_t even_w = odd ? nb[4 + k] : own[k];   // the even voxel's two channels
+            const uint32_t odd_w = odd ? own[4 + k] : nb[k];    // the odd voxel's two channels
+            const int c = 2 * k + (odd ? 8 : 0);
+            if (c < 4 * gq) {
+                gy32[c * (GSTR / 2) + (v >> 1)] = (even_w & 0xffffu) | (odd_w << 16);
+                gy32[(c + 1) * (GSTR / 2) + (v >> 1)] = (even_w >> 16) | (odd_w & 0xffff0000u);
+            }
         }
     };
 
     // v_mfma_f32_16x16x32_bf16, two K-steps of 32 voxels per slice: lane
-    // (q, r16) takes input channel c0 + r16 and the 8 voxels x = 8 (q & 1) ..
-    // + 7 of row y = 2 m + (q >> 1) (an even halo index, so 4-byte aligned)
-    const int xq = 8 * (q & 1), yq = q >> 1;
-    const uint16_t* hl = halo + r16 * NHALO + (wave * HY + yq) * HX + xq;
-    const uint16_t* gl = gy + r16 * NB + wave * (BX * BY) + yq * BX + xq;
+    // (q, r16) takes input channel c0 + r16 and the 8 voxels x = 8 (q >> 1) ..
+    // + 7 of row y = 2 m + (q & 1) (an even halo index, so 4-byte aligned)
+    const int xq = 8 * (q >> 1), yq = q & 1;
+    const uint16_t* hl = halo + r16 * HSTR + (wave * HY + yq) * HX + xq;
+    const uint16_t* gl = gy + r16 * GSTR + wave * (BX * BY) + yq * BX + xq;
     int64_t br = blockIdx.x;
     if (br < nbricks) fetch(br);
     for (; br < nbricks; br += nparts) {

@@ -127,16 +127,125 @@ def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str)
     return "\n".join(out) + "\n"
 
 
+def _per_kernel(run_dir: str, patterns) -> dict:
+    """{kernel name: {counter: [values per dispatch]}} of the kernels whose
+    names contain one of the patterns, and the largest value per counter of
+    the copy probe."""
+    out, copy = {}, {}
+    with open(_one(os.path.join(run_dir, "**", "*counter_collection.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            name, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+            if COPY in name:
+                copy[c] = max(copy.get(c, 0.0), v)
+            elif any(p in name for p in patterns):
+                out.setdefault(name, {}).setdefault(c, []).append(v)
+    return out, copy
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").replace("lbmnet_dev::", "")[:70]
+
+
+def summarize_kernels(folder: str, patterns, copy_mib: int, cmd: str, pmc_runs) -> str:
+    """Per-kernel summary of a group of kernels (names containing one of the
+    patterns): launches and average duration (trace run), HBM bytes per
+    dispatch from FETCH_SIZE / WRITE_SIZE scaled by the copy probe, the
+    bandwidth that gives, and the per-dispatch means of the counters of the
+    extra runs pmc_runs = [(subfolder, command options)]."""
+    rows, _, _ = step_stats_for(os.path.join(folder, "trace"), patterns)
+    fetch, fcopy = _per_kernel(os.path.join(folder, "fetch"), patterns)
+    write, wcopy = _per_kernel(os.path.join(folder, "write"), patterns)
+    moved_kib = copy_mib * 1024.0
+    fs, ws = moved_kib / fcopy["FETCH_SIZE"], moved_kib / wcopy["WRITE_SIZE"]
+    extra = [(sub, _per_kernel(os.path.join(folder, sub), patterns)[0]) for sub, _ in pmc_runs]
+    out = [f"# rocprofv3 summary of the kernels matching {list(patterns)}",
+           f"# kernel trace command : rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run -- {cmd}",
+           f"# FETCH_SIZE command   : rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {cmd}",
+           f"# WRITE_SIZE command   : rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {cmd}"]
+    for sub, opts in pmc_runs:
+        out.append(f"# {sub} command{' ' * max(1, 14 - len(sub))}: rocprofv3 {opts} --output-format csv -d <dir>/{sub} "
+                   f"-o run -- {cmd}")
+    out += [f"# copy calibration: FETCH_SIZE x {fs:.3f}, WRITE_SIZE x {ws:.3f} (a plain {copy_mib} MiB device copy)",
+            "#", "# kernel                                                                 calls   avg us  "
+            "read MB  write MB   GB/s   per-dispatch counter means"]
+    for name, calls, avg, _, _ in sorted(rows, key=lambda r: -r[1] * r[2]):
+        rd = fs * _mean(fetch.get(name, {}).get("FETCH_SIZE")) * 1024.0
+        wr = ws * _mean(write.get(name, {}).get("WRITE_SIZE")) * 1024.0
+        ctr = []
+        for _, d in extra:
+            for c, vals in sorted(d.get(name, {}).items()):
+                ctr.append(f"{c} {_mean(vals):.4g}")
+        out.append(f"#   {_short(name):70s} {calls:6d} {avg:8.2f} {rd / 1e6:8.2f} {wr / 1e6:9.2f} "
+                   f"{(rd + wr) / (avg * 1e-6) / 1e9:7.1f}   {'; '.join(ctr)}")
+    return "\n".join(out) + "\n"
+
+
+def conv_gflop(coarse_voxels: int) -> tuple:
+    """Useful convolution GFLOP of one network forward over coarse_voxels
+    coarse voxels (2 x 27 x c_in x c_out per output voxel and layer, the
+    half level holding 1/8 and the fine level 8 times the coarse voxels),
+    and of one training step on it (forward, weight gradient, and input
+    gradient of every layer but the first)."""
+    from .net import layer_table
+    scale = {0: 1.0, 1: 1.0 / 8.0, 2: 8.0}
+    per = [2.0 * 27 * ci * co * coarse_voxels * scale[lev] / 1e9 for _, ci, co, _, lev, _ in layer_table()]
+    return sum(per), 3.0 * sum(per) - per[0]
+
+
+def conv_efficiency(trace_dir: str, train_steps: int, crop_voxels: int, forwards: int, grid_voxels: int) -> list:
+    """Lines: convolution kernel time of the run, useful FLOPs, TFLOP/s and
+    the fraction of the 2.5 PFLOP/s BF16 dense MFMA peak."""
+    rows, _, _ = step_stats_for(trace_dir, ["k_conv"])
+    secs = sum(c * a for _, c, a, _, _ in rows) * 1e-6
+    _, train_g = conv_gflop(crop_voxels)
+    fwd_g, _ = conv_gflop(grid_voxels)
+    total = train_steps * train_g + forwards * fwd_g
+    tf = total / 1e3 / secs
+    return [f"# useful convolution flops: training step {train_g:.1f} GFLOP ({crop_voxels} coarse voxels), "
+            f"full-grid forward {fwd_g:.1f} GFLOP ({grid_voxels} coarse voxels)",
+            f"# {train_steps} training steps + {forwards} forwards: {total / 1e3:.2f} TFLOP in {secs * 1e3:.1f} ms of "
+            f"convolution kernels -> {tf:.1f} TFLOP/s ({100 * tf / 2500:.2f} % of the 2.5 PFLOP/s BF16 dense peak)",
+            f"conv_tflops_achieved: {tf:.2f}",
+            f"conv_kernel_seconds: {secs:.4f}"]
+
+
+def _mean(vals):
+    return sum(vals) / len(vals) if vals else float("nan")
+
+
+def step_stats_for(trace_dir: str, patterns) -> tuple:
+    rows = []
+    with open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            if any(p in r["Name"] for p in patterns):
+                rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                             float(r["MaxNs"]) / 1e3))
+    return rows, None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dir", required=True)
-    ap.add_argument("--storage", required=True, choices=list(POP_BYTES))
-    ap.add_argument("--workload", required=True)
+    ap.add_argument("--storage", choices=list(POP_BYTES))
+    ap.add_argument("--workload")
+    ap.add_argument("--kernels", default=None,
+                    help="comma-separated name patterns: summarize those kernels instead of the step kernel")
+    ap.add_argument("--pmc-run", action="append", default=[],
+                    help="extra counter run as subfolder=rocprofv3 options (repeatable)")
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--conv-flops", default=None,
+                    help="train_steps,crop_coarse_voxels,forwards,grid_coarse_voxels: add the convolution efficiency")
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    text = summarize(a.dir, a.storage, a.workload, a.copy_mib, a.cmd)
+    if a.kernels:
+        runs = [tuple(r.split("=", 1)) for r in a.pmc_run]
+        text = summarize_kernels(a.dir, a.kernels.split(","), a.copy_mib, a.cmd, runs)
+        if a.conv_flops:
+            ts, cv, fw, gv = (int(v) for v in a.conv_flops.split(","))
+            text += "\n".join(conv_efficiency(os.path.join(a.dir, "trace"), ts, cv, fw, gv)) + "\n"
+    else:
+        text = summarize(a.dir, a.storage, a.workload, a.copy_mib, a.cmd)
     with open(a.out, "w") as fh:
         fh.write(text)
     print(text, end="")
