@@ -239,34 +239,49 @@ def cpu_model():
     return "unknown"
 
 
-def _time_oracle(case, threads, budget_s):
-    from oracle import o2
-    sim = o2.O2Sim(case, nthreads=threads)
+_ORACLE_TIMER = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import synth
+from oracle import o2
+size, threads, budget = int(sys.argv[2]), int(sys.argv[3]), float(sys.argv[4])
+case = synth.aneurysm_case(size, seed=0)
+sim = o2.O2Sim(case, nthreads=threads)
+sim.run(1)
+t0 = time.perf_counter()
+steps = 0
+while time.perf_counter() - t0 < budget:
     sim.run(1)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s:
-        sim.run(1)
-        steps += 1
-    dt = time.perf_counter() - t0
-    return sim.n, steps, dt
+    steps += 1
+print(json.dumps({"n": sim.n, "steps": steps, "seconds": time.perf_counter() - t0, "name": case.name}))
+"""
 
 
-def cpu_baseline(case, budget_s):
-    """Oracle tier O2 (FP64, C with OpenMP) on the same case, stepped from rest
-    for about budget_s seconds on every host thread this process may use, then
-    for about budget_s / 2 seconds on one thread."""
+def _time_oracle(size, threads, budget_s):
+    """Step the oracle from rest for about budget_s seconds in a child
+    process that loads neither torch nor the GPU library (their idle worker
+    threads would compete with the oracle's for the host cores)."""
+    import subprocess
+    res = subprocess.run([sys.executable, "-c", _ORACLE_TIMER, ROOT, str(size), str(threads), str(budget_s)],
+                         capture_output=True, text=True, check=True, timeout=600)
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(size, budget_s):
+    """Oracle tier O2 (FP64, C with OpenMP) on the same aneurysm geometry,
+    stepped from rest for about budget_s seconds on every host thread this
+    process may use, then for about budget_s / 2 seconds on one thread."""
     from oracle import o2
     o2.build(force=False)
     threads = host_threads()
-    n, steps, dt = _time_oracle(case, threads, budget_s)
-    n1, steps1, dt1 = _time_oracle(case, 1, 0.5 * budget_s)
-    return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+    r = _time_oracle(size, threads, budget_s)
+    r1 = _time_oracle(size, 1, 0.5 * budget_s)
+    return {"value": round(r["n"] * r["steps"] / r["seconds"] / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{case.name}: {steps} steps of the FP64 C/OpenMP oracle from rest "
-                      f"({n} fluid nodes, {dt:.1f} s, {threads} threads); "
-                      f"{steps1} steps on 1 thread ({dt1:.1f} s)",
-            "single_thread_value": round(n1 * steps1 / dt1 / 1e6, 3),
+            "sample": f"{r['name']}: {r['steps']} steps of the FP64 C/OpenMP oracle from rest "
+                      f"({r['n']} fluid nodes, {r['seconds']:.1f} s, {threads} threads); "
+                      f"{r1['steps']} steps on 1 thread ({r1['seconds']:.1f} s)",
+            "single_thread_value": round(r1["n"] * r1["steps"] / r1["seconds"] / 1e6, 3),
             "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count()}
 
 
@@ -422,7 +437,7 @@ def main():
         line["also"] = also
 
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(size, args.cpu_seconds)
         note(f"cpu baseline: {line['cpu_baseline']['value']} MLUPS")
     print(json.dumps(line), flush=True)
 
