@@ -206,8 +206,10 @@ def corrector_bench():
             "speedup_vs_fine_f32": round(res["speedup_vs_fine_f32"], 2)}
 
 
-def roofline(n, ms_per_step, storage, traffic):
-    alg = 54 * POP_BYTES[storage] * n                 # algorithmic bytes per launch
+def roofline(n, ms_per_step, storage, traffic, wall_links=0):
+    # algorithmic bytes per launch: 54 populations per node, plus one
+    # curved-wall weight per wall link (8 B with FP64 storage, 4 B otherwise)
+    alg = 54 * POP_BYTES[storage] * n + (8 if storage == "f64" else 4) * wall_links
     achieved = alg / (ms_per_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -248,11 +250,17 @@ size, threads, budget = int(sys.argv[2]), int(sys.argv[3]), float(sys.argv[4])
 case = synth.aneurysm_case(size, seed=0)
 sim = o2.O2Sim(case, nthreads=threads)
 sim.run(1)
+# each call ends with a serial mass and momentum sum: size the timed call
+# from the difference of a one-step and a three-step call, and time all its
+# steps in one call
 t0 = time.perf_counter()
-steps = 0
-while time.perf_counter() - t0 < budget:
-    sim.run(1)
-    steps += 1
+sim.run(1)
+t1 = time.perf_counter()
+sim.run(3)
+per_step = max(1e-6, 0.5 * ((time.perf_counter() - t1) - (t1 - t0)))
+steps = max(2, int(budget / per_step))
+t0 = time.perf_counter()
+sim.run(steps)
 print(json.dumps({"n": sim.n, "steps": steps, "seconds": time.perf_counter() - t0, "name": case.name}))
 """
 
@@ -303,6 +311,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(POP_BYTES))
     ap.add_argument("--workload", default="aneurysm512", choices=["aneurysm256", "aneurysm512"],
                     help="geometry of the timed run (the 256^3 one is Infinity Cache resident)")
+    ap.add_argument("--walls", default="halfway", choices=["halfway", "curved"],
+                    help="wall rule of the timed run: halfway bounce-back, or interpolated bounce-back with the "
+                         "exact wall distance on every wall link (Eq. (9)-(10))")
     ap.add_argument("--no-extra", action="store_true", help="skip the other storage forms and sizes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector protocol")
@@ -310,6 +321,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
+    if args.walls == "curved" and not args.no_extra:
+        ap.error("--walls curved times the curved-wall step alone: add --no-extra")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the method's multi-GPU "
               "decomposition is not built.", file=sys.stderr)
@@ -328,10 +341,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    workload = args.workload
-    size = 256 if workload == "aneurysm256" else 512
+    size = 256 if args.workload == "aneurysm256" else 512
     case = synth.aneurysm_case(size, seed=0)
-    main_run = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=not args.no_extra)
+    wall_q, nlinks = None, 0
+    workload = args.workload
+    if args.walls == "curved":
+        links = synth.wall_links(case.mask, case.periodic)
+        wall_q, nlinks = (links, synth.wall_distances(case, links)), int(len(links))
+        workload += "_curved"
+    main_run = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=not args.no_extra,
+                        wall_q=wall_q)
     note(f"{workload} {args.storage}: {main_run['mlups']:.1f} MLUPS, {main_run['ms_per_step'] * 1e3:.2f} us per step")
     traffic = read_traffic(args.storage, workload)
     line = {
@@ -347,11 +366,13 @@ def main():
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": f"{workload}_seed0_womersley_alpha3_period{case.period}", "box": [size] * 3,
+        "config": {"workload": f"{args.workload}_seed0_womersley_alpha3_period{case.period}", "box": [size] * 3,
                    "fluid_nodes": main_run["n"], "storage": args.storage, "tau": round(case.tau, 6),
-                   "steps_per_graph": 16},
-        "roofline": roofline(main_run["n"], main_run["ms_per_step"], args.storage, traffic),
+                   "steps_per_graph": 16, "walls": args.walls},
+        "roofline": roofline(main_run["n"], main_run["ms_per_step"], args.storage, traffic, nlinks),
     }
+    if nlinks:
+        line["config"]["wall_links"] = nlinks
     prof = read_profile(args.storage, workload)
     if prof.get("avg_step_kernel_us"):
         # kernel-only average of the committed rocprofv3 trace (the event figure

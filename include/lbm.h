@@ -110,8 +110,10 @@ int lbm_create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned peri
  * be fluid, otherwise that link keeps halfway bounce-back.  The wall force of
  * a curved link is (f*_alpha(x, t) + f_abar(x, t + 1)) c_alpha.  Links not
  * listed keep halfway bounce-back.  The arrays are host memory, read during
- * the call.  Nodes with curved links take the explicit-offset path of the
- * step (slower than the bitmap path).  Errors: EINVAL for a link that is out
+ * the call.  The step blends each wall link's bounce-back value with its
+ * second value after the gather, from one weight per wall link held in device
+ * memory (the link count times the size of the arithmetic type: 8 bytes for
+ * LBM_F64, 4 otherwise).  Errors: EINVAL for a link that is out
  * of range, does not start at a fluid cell or end at a wall, is listed twice,
  * or has q outside (0, 1]; otherwise as lbm_create_domain. */
 int lbm_create_domain_curved(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic_bits,

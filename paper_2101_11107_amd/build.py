@@ -11,9 +11,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
-# (source, extra flags, object name): the batch kernels compile once per
-# storage type, in parallel
+# (source, extra flags, object name): the step and batch kernels compile once
+# per storage type, in parallel
 SOURCES = [("lbm_kernels.hip", [], "lbm_kernels"), ("lbm_net.hip", [], "lbm_net"), ("lbm_net_noalloc.hip", [], "lbm_net_noalloc"),
+           *[("lbm_step.hip", [f"-DLBM_STEP_STORAGE={k}"], f"lbm_step_{k}") for k in range(4)],
            *[("lbm_batch.hip", [f"-DLBM_BATCH_STORAGE={k}"], f"lbm_batch_{k}") for k in range(4)],
            ("lbm_api.cpp", [], "lbm_api"), ("lbm_batch_api.cpp", [], "lbm_batch_api"),
            ("lbm_net_api.cpp", [], "lbm_net_api")]

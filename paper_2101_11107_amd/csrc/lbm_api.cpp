@@ -108,8 +108,8 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.link_meta = (const int32_t*)(base + d->off_lmeta);
     a.link_coef = (const double*)(base + d->off_lcoef);
     a.link_add = (double*)(base + d->off_ladd);
-    a.link_wq = (const double*)(base + d->off_lwq);
-    a.link_off2 = (const uint32_t*)(base + d->off_loff2);
+    a.crec = d->crec.empty() ? nullptr : base + d->off_crec;
+    a.crec_base = (const uint32_t*)(base + d->off_cbase);
     a.tcount = (int64_t*)(base + d->off_tcount);
     a.trig = (double*)(base + d->off_trig);
     a.cos_w = std::cos(d->omega);
@@ -249,13 +249,8 @@ int launch_steps_eager(lbm_domain* d, int nsteps) {
     const bool big = 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES;
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
-        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(), big, d->collision == 1};
-        if (!d->pre.empty())
-            HIP_TRY(lbm::launch_curved_pre(d->storage, const_cast<void*>(a.fin),
-                                           (const lbm::CurvedLink*)(d->dev + d->off_pre), (int64_t)d->pre.size(),
-                                           v.monitor ? a.partials + (size_t)d->nblocks * lbm::MON_WORDS : nullptr,
-                                           d->stream),
-                    "curved-wall pass");
+        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(), big, d->collision == 1,
+                                 !d->crec.empty()};
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
         d->cur ^= 1;
     }
@@ -386,6 +381,15 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         const bool per[3] = {(periodic_bits & 1) != 0, (periodic_bits & 2) != 0, (periodic_bits & 4) != 0};
         const bool per_yz = per[1] || per[2];
         int64_t i = 0;
+        // curved walls: per ordinary node, its wall links (bit alpha) and the
+        // offset of its weights in cw (in increasing alpha)
+        std::vector<uint32_t> node_fw;
+        std::vector<int64_t> cw_off;
+        std::vector<double> cw;
+        if (wq) {
+            node_fw.assign((size_t)npad, 0u);
+            cw_off.assign((size_t)npad, 0);
+        }
         // Curved-wall link of node i at (x, y, z), incoming direction a, abar =
         // 26 - a towards the wall (Eq. (9)-(10), linear interpolation):
         //   q <  1/2: 2q f*_abar(x) + (1 - 2q) f*_abar(x + c_a)
@@ -454,33 +458,30 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                         if (xwrap && kind[a] == LBM_FLUID) special = true;
                         if (wq && kind[a] == LBM_SOLID && wq->count(d->cell(x, y, z) * 27 + a)) curved |= 1u << a;
                     }
-                    // Curved links of an ordinary node go to the pass before the
-                    // step, which rewrites f*_abar(x) of each in place.  A link
-                    // with q >= 1/2 reads f*_a(x), which that pass rewrites when
-                    // the link of direction abar is curved too (a one-cell gap):
-                    // such nodes take the explicit-offset path.
-                    if (curved && !special) {
-                        for (int a = 0; a < 27; ++a)
-                            if (((curved >> a) & 1u) && ((curved >> (26 - a)) & 1u) &&
-                                wq->at(d->cell(x, y, z) * 27 + a) >= 0.5)
-                                special = true;
-                    }
                     if (d->index_of(x, y, z) != i) return fail(LBM_EINVAL, "internal: index mismatch");
+                    if (wq) {
+                        // one signed weight per wall link, in increasing alpha
+                        // (halfway links 1; curved: w0, negative for q >= 1/2)
+                        uint32_t fw = 0;
+                        cw_off[i] = (int64_t)cw.size();
+                        for (int a = 0; a < 27; ++a) {
+                            if (kind[a] != LBM_SOLID) continue;
+                            fw |= 1u << a;
+                            double r = 1.0;
+                            if ((curved >> a) & 1u) {
+                                double w0, w1;
+                                int64_t node2;
+                                int plane2;
+                                curved_weights(x, y, z, i, a, w0, w1, node2, plane2);
+                                r = plane2 == a ? -w0 : w0;
+                            }
+                            cw.push_back(r);
+                        }
+                        node_fw[i] = fw;
+                    }
                     if (!special) {
                         d->node_words[i] = per_yz ? ((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20))
                                                   : ((uint32_t)x | ((uint32_t)d->row_of(y, z) << 10));
-                        for (int a = 0; a < 27; ++a) {
-                            if (!((curved >> a) & 1u)) continue;
-                            lbm::CurvedLink cl{};
-                            int64_t node2;
-                            int plane2;
-                            curved_weights(x, y, z, i, a, cl.w0, cl.w1, node2, plane2);
-                            cl.dst = (uint32_t)i;            // element indices; bytes once the layout is fixed
-                            cl.src2 = (uint32_t)node2;
-                            cl.dir = a;
-                            d->pre.push_back(cl);
-                            d->pre_src_plane.push_back(plane2);
-                        }
                     } else {
                         SpecialNode sp{};
                         sp.node = (int32_t)i;
@@ -496,8 +497,7 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                                 sp.off[a] = (uint32_t)i;
                                 d->spec_plane.push_back(26 - a);
                                 if (kind[a] == LBM_SOLID) {
-                                    if (wq && wq->count(d->cell(x, y, z) * 27 + a)) sp.qmask |= 1u << a;
-                                    else sp.wallmask |= 1u << a;
+                                    sp.wallmask |= 1u << a;
                                 } else {
                                     const int32_t type = kind[a] == LBM_INLET ? lbm::LINK_INLET : lbm::LINK_OUTLET;
                                     if (type == lbm::LINK_INLET) d->has_inlet_links = true;
@@ -507,41 +507,36 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
                                     d->link_xyz.push_back(y);
                                     d->link_xyz.push_back(z);
                                     for (int q = 0; q < lbm::LINK_COEFS; ++q) d->link_coef.push_back(0.0);
-                                    d->link_wq.push_back(0.0);
-                                    d->link_wq.push_back(0.0);
-                                    d->link_off2.push_back(0u);
-                                    d->link_off2_plane.push_back(0);
                                 }
                             }
-                        }
-                        // curved-wall links (Eq. (9)-(10), linear interpolation), with
-                        // abar = 26 - a the direction towards the wall:
-                        //   q <  1/2: 2q f*_abar(x) + (1 - 2q) f*_abar(x + c_a)
-                        //   q >= 1/2: f*_abar(x) / 2q + (2q - 1) / 2q f*_a(x)
-                        // where x + c_a (the node behind x) must be fluid, else the
-                        // link keeps halfway bounce-back (weights 1, 0).
-                        for (int a = 0; a < 27; ++a) {
-                            if (!((sp.qmask >> a) & 1u)) continue;
-                            double w0, w1;
-                            int64_t node2;
-                            int plane2;
-                            curved_weights(x, y, z, i, a, w0, w1, node2, plane2);
-                            d->link_meta.push_back(lbm::LINK_WALL_Q | (a << 8));
-                            d->link_xyz.push_back(x);
-                            d->link_xyz.push_back(y);
-                            d->link_xyz.push_back(z);
-                            for (int k = 0; k < lbm::LINK_COEFS; ++k) d->link_coef.push_back(0.0);
-                            d->link_wq.push_back(w0);
-                            d->link_wq.push_back(w1);
-                            d->link_off2.push_back((uint32_t)node2);
-                            d->link_off2_plane.push_back(plane2);
-                            ++d->ncurved;
                         }
                         d->spec.push_back(sp);
                         d->node_words[i] = lbm::SPECIAL_BIT | (uint32_t)sidx;
                     }
                     ++i;
             }
+        }
+
+        // curved-wall records in the step's order: per 64-node chunk (one
+        // wavefront), per incoming direction, per node
+        if (wq && !cw.empty()) {
+            const int64_t chunks = npad / lbm::CREC_CHUNK;
+            d->crec_base.assign((size_t)chunks, 0u);
+            d->crec.reserve(cw.size());
+            for (int64_t c = 0; c < chunks; ++c) {
+                d->crec_base[(size_t)c] = (uint32_t)d->crec.size();
+                const int64_t i0 = c * lbm::CREC_CHUNK, i1 = std::min<int64_t>(nfluid, i0 + lbm::CREC_CHUNK);
+                for (int a = 0; a < 27; ++a)
+                    for (int64_t k = i0; k < i1; ++k) {
+                        const uint32_t fw = node_fw[(size_t)k];
+                        if ((fw >> a) & 1u)
+                            d->crec.push_back(cw[(size_t)(cw_off[(size_t)k] + __builtin_popcount(fw & ((1u << a) - 1u)))]);
+                    }
+            }
+            if (d->crec.size() != cw.size()) return fail(LBM_EINVAL, "internal: curved-wall record count mismatch");
+            if (d->crec.size() >= ((size_t)1 << 31)) return fail(LBM_EINVAL, "too many wall links");
+            // the arithmetic type of the 2- and 4-byte storage forms
+            if (storage != LBM_F64) d->crec_f32.assign(d->crec.begin(), d->crec.end());
         }
 
         // device layout
@@ -560,22 +555,6 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
             }
         d->spec_plane.clear();
         d->spec_plane.shrink_to_fit();
-        for (size_t k = 0; k < d->pre.size(); ++k) {
-            lbm::CurvedLink& cl = d->pre[k];
-            cl.dst = (uint32_t)((uint64_t)lbm::pop_index(cl.dst, (uint32_t)(26 - cl.dir), (uint32_t)npad, (uint32_t)sb) * sb);
-            cl.src2 = (uint32_t)((uint64_t)lbm::pop_index(cl.src2, (uint32_t)d->pre_src_plane[k], (uint32_t)npad, (uint32_t)sb) * sb);
-        }
-        d->pre_src_plane.clear();
-        d->pre_src_plane.shrink_to_fit();
-        // in address order: neighbouring threads then touch neighbouring
-        // populations (the links are independent)
-        std::sort(d->pre.begin(), d->pre.end(),
-                  [](const lbm::CurvedLink& p, const lbm::CurvedLink& q) { return p.dst < q.dst; });
-        d->pre_blocks = (int)((d->pre.size() + lbm::BLOCK - 1) / lbm::BLOCK);
-        for (size_t k = 0; k < d->link_off2.size(); ++k)
-            d->link_off2[k] = (uint32_t)((uint64_t)lbm::pop_index(d->link_off2[k], (uint32_t)d->link_off2_plane[k], (uint32_t)npad, (uint32_t)sb) * sb);
-        d->link_off2_plane.clear();
-        d->link_off2_plane.shrink_to_fit();
         d->off_popA = take(d->pop_bytes);
         d->off_popB = take(d->pop_bytes);
         d->off_node = take((size_t)npad * 4);
@@ -585,16 +564,15 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->off_lmeta = take(nl * sizeof(int32_t));
         d->off_lcoef = take(nl * lbm::LINK_COEFS * sizeof(double));
         d->off_ladd = take(nl * sizeof(double));
-        d->off_lwq = take(nl * 2 * sizeof(double));
-        d->off_loff2 = take(nl * sizeof(uint32_t));
         d->off_tcount = take(2 * sizeof(int64_t));
         d->off_trig = take(4 * sizeof(double));
         // monitor partials: one per work-group, for work-groups down to 64 nodes
-        d->off_part = take((size_t)(npad / 64 + 1 + d->pre_blocks) * lbm::MON_WORDS * sizeof(double));
+        d->off_part = take((size_t)(npad / 64 + 1) * lbm::MON_WORDS * sizeof(double));
         d->off_monout = take(lbm::MON_WORDS * sizeof(double));
         d->off_avg = take((size_t)3 * nfluid * sizeof(double));
         d->off_probe = take(lbm::MAX_PROBES * sizeof(int32_t));
-        d->off_pre = take(std::max<size_t>(1, d->pre.size()) * sizeof(lbm::CurvedLink));
+        d->off_crec = take(std::max<size_t>(1, d->crec.size()) * (storage == LBM_F64 ? 8 : 4));
+        d->off_cbase = take(std::max<size_t>(1, d->crec_base.size()) * sizeof(uint32_t));
         d->dev_bytes = off;
     } catch (const std::bad_alloc&) {
         delete d;
@@ -738,16 +716,19 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     if (!d->spec.empty())
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_spec, d->spec.data(), d->spec.size() * sizeof(SpecialNode),
                                hipMemcpyHostToDevice, st), "upload of special nodes");
-    if (!d->pre.empty())
-        HIP_TRY(hipMemcpyAsync(d->dev + d->off_pre, d->pre.data(), d->pre.size() * sizeof(lbm::CurvedLink),
-                               hipMemcpyHostToDevice, st), "upload of curved-wall links");
+    if (!d->crec.empty()) {
+        if (d->storage == LBM_F64)
+            HIP_TRY(hipMemcpyAsync(d->dev + d->off_crec, d->crec.data(), d->crec.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, st), "upload of curved-wall weights");
+        else
+            HIP_TRY(hipMemcpyAsync(d->dev + d->off_crec, d->crec_f32.data(), d->crec_f32.size() * sizeof(float),
+                                   hipMemcpyHostToDevice, st), "upload of curved-wall weights");
+        HIP_TRY(hipMemcpyAsync(d->dev + d->off_cbase, d->crec_base.data(), d->crec_base.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, st), "upload of curved-wall record index");
+    }
     if (d->nlinks()) {
         HIP_TRY(hipMemcpyAsync(d->dev + d->off_lmeta, d->link_meta.data(), d->nlinks() * sizeof(int32_t),
                                hipMemcpyHostToDevice, st), "upload of link table");
-        HIP_TRY(hipMemcpyAsync(d->dev + d->off_lwq, d->link_wq.data(), d->link_wq.size() * sizeof(double),
-                               hipMemcpyHostToDevice, st), "upload of curved-wall weights");
-        HIP_TRY(hipMemcpyAsync(d->dev + d->off_loff2, d->link_off2.data(), d->link_off2.size() * sizeof(uint32_t),
-                               hipMemcpyHostToDevice, st), "upload of curved-wall offsets");
     }
     d->links_dirty = true;
     d->initialized = false;
@@ -985,7 +966,7 @@ int lbm_monitors(lbm_domain* d, double out[10]) {
     if (!d || !out) return fail(LBM_EINVAL, "NULL argument");
     if (!d->monitored) return fail(LBM_ESTATE, "no step has run since initialisation");
     double* mo = (double*)(d->dev + d->off_monout);
-    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->mon_blocks + d->pre_blocks, mo,
+    HIP_TRY(lbm::launch_monitor_finalize((const double*)(d->dev + d->off_part), d->mon_blocks, mo,
                                          d->stream),
             "monitor reduction");
     HIP_TRY(hipMemcpyAsync(d->mon_host, mo, 9 * sizeof(double), hipMemcpyDeviceToHost, d->stream), "monitor copy");

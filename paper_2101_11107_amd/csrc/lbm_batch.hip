@@ -16,7 +16,7 @@ namespace {
 // Bound of a barrier wait (iterations of a ~100-cycle sleep, about 0.2 s).
 constexpr unsigned SPIN_LIMIT = 1u << 21;
 
-template <class S, bool MON, bool ONE, bool NT, int BS>
+template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR>
 __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int step) {
     const int packed = b.item_map[item];
     StepArgs a = b.doms[packed >> ITEM_DOMAIN_SHIFT];
@@ -32,24 +32,24 @@ __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int ste
     // domain's own step would (the forms round differently).
     const bool one = ONE || (a.collision == 0 && a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0);
     if (one) {
-        if (a.periodic & 6) step_block<S, MON, 1, true, NT, BS>(a, lb);
-        else step_block<S, MON, 1, false, NT, BS>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 1, true, NT, BS, CUR>(a, lb);
+        else step_block<S, MON, 1, false, NT, BS, CUR>(a, lb);
     } else if (a.collision == 1) {
-        if (a.periodic & 6) step_block<S, MON, 2, true, NT, BS>(a, lb);
-        else step_block<S, MON, 2, false, NT, BS>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 2, true, NT, BS, CUR>(a, lb);
+        else step_block<S, MON, 2, false, NT, BS, CUR>(a, lb);
     } else {
-        if (a.periodic & 6) step_block<S, MON, 0, true, NT, BS>(a, lb);
-        else step_block<S, MON, 0, false, NT, BS>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 0, true, NT, BS, CUR>(a, lb);
+        else step_block<S, MON, 0, false, NT, BS, CUR>(a, lb);
     }
 }
 
-template <class S, bool MON, bool ONE, bool NT, int BS>
+template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR>
 __global__ __launch_bounds__(BS) void k_batch_step(BatchArgs b, int step) {
     // XCD-aware order as in the single-domain kernel
     const int hb = blockIdx.x;
     const int item = (hb & 7) * b.items_per_xcd + (hb >> 3);
     if (item >= b.nitems) return;
-    batch_item<S, MON, ONE, NT, BS>(b, item, step);
+    batch_item<S, MON, ONE, NT, BS, CUR>(b, item, step);
 }
 
 // Device-wide barrier for epoch e (1, 2, ... within one launch; the host clears
@@ -108,33 +108,33 @@ __device__ bool grid_barrier(const BatchArgs& b, unsigned epoch) {
 
 // Steps step0 .. step0 + nsteps - 1 without monitors (the monitored last step
 // of a sequence is a k_batch_step launch).
-template <class S, bool ONE, bool NT, int BS>
+template <class S, bool ONE, bool NT, int BS, bool CUR>
 __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs b, int step0, int nsteps) {
     for (int s = 0; s < nsteps; ++s) {
         for (int item = blockIdx.x; item < b.nitems; item += gridDim.x)
-            batch_item<S, false, ONE, NT, BS>(b, item, step0 + s);
+            batch_item<S, false, ONE, NT, BS, CUR>(b, item, step0 + s);
         if (s + 1 < nsteps && !grid_barrier(b, (unsigned)(s + 1))) return;
     }
 }
 
-template <class S, bool ONE, bool NT, int BS>
+template <class S, bool ONE, bool NT, int BS, bool CUR>
 hipError_t step_bs(const BatchArgs& b, int step, bool monitor, hipStream_t st) {
     const dim3 grid(8 * b.items_per_xcd), block(BS);
-    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS>), grid, block, 0, st, b, step);
-    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS>), grid, block, 0, st, b, step);
+    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS, CUR>), grid, block, 0, st, b, step);
+    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS, CUR>), grid, block, 0, st, b, step);
     return hipGetLastError();
 }
 
-template <class S, bool ONE, bool NT, int BS>
+template <class S, bool ONE, bool NT, int BS, bool CUR>
 hipError_t persistent_bs(const BatchArgs& b, int grid, int step0, int nsteps, hipStream_t st) {
-    hipLaunchKernelGGL((k_batch_persistent<S, ONE, NT, BS>), dim3(grid), dim3(BS), 0, st, b, step0, nsteps);
+    hipLaunchKernelGGL((k_batch_persistent<S, ONE, NT, BS, CUR>), dim3(grid), dim3(BS), 0, st, b, step0, nsteps);
     return hipGetLastError();
 }
 
-template <class S, bool ONE, bool NT, int BS>
+template <class S, bool ONE, bool NT, int BS, bool CUR>
 hipError_t capacity_bs(int* blocks) {
     int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<S, ONE, NT, BS>, BS, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<S, ONE, NT, BS, CUR>, BS, 0);
     if (e != hipSuccess) return e;
     e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -144,61 +144,65 @@ hipError_t capacity_bs(int* blocks) {
     return hipSuccess;
 }
 
-// Dispatch over (rates_one, stream_store, block); F is called as F<S, ONE, NT, BS>().
-#define BATCH_BS(S, ONE, NT, F, ...)                                              \
+// Dispatch over (kind, stream_store, block); F is called as F<S, ONE, NT, BS, CUR>().
+#define BATCH_BS(S, ONE, NT, CUR, F, ...)                                         \
     switch (c.block) {                                                            \
-        case 128: return F<S, ONE, NT, 128>(__VA_ARGS__);                         \
-        case 256: return F<S, ONE, NT, 256>(__VA_ARGS__);                         \
-        case 512: return F<S, ONE, NT, 512>(__VA_ARGS__);                         \
+        case 128: return F<S, ONE, NT, 128, CUR>(__VA_ARGS__);                    \
+        case 256: return F<S, ONE, NT, 256, CUR>(__VA_ARGS__);                    \
+        case 512: return F<S, ONE, NT, 512, CUR>(__VA_ARGS__);                    \
         default: return hipErrorInvalidValue;                                     \
     }
+#define BATCH_NT(S, ONE, CUR, F, ...)                                             \
+    if constexpr (sizeof(S) >= 4) {                                               \
+        if (c.stream_store) BATCH_BS(S, ONE, true, CUR, F, __VA_ARGS__)          \
+    }                                                                             \
+    BATCH_BS(S, ONE, false, CUR, F, __VA_ARGS__)
 
-template <class S, bool ONE>
+template <class S, bool ONE, bool CUR>
 hipError_t step_one(const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
-    if constexpr (sizeof(S) >= 4) {
-        if (c.stream_store) BATCH_BS(S, ONE, true, step_bs, b, step, monitor, st)
-    }
-    BATCH_BS(S, ONE, false, step_bs, b, step, monitor, st)
+    BATCH_NT(S, ONE, CUR, step_bs, b, step, monitor, st)
 }
 
-template <class S, bool ONE>
+template <class S, bool ONE, bool CUR>
 hipError_t persistent_one(const BatchArgs& b, const BatchConfig& c, int grid, int step0, int nsteps, hipStream_t st) {
-    if constexpr (sizeof(S) >= 4) {
-        if (c.stream_store) BATCH_BS(S, ONE, true, persistent_bs, b, grid, step0, nsteps, st)
-    }
-    BATCH_BS(S, ONE, false, persistent_bs, b, grid, step0, nsteps, st)
+    BATCH_NT(S, ONE, CUR, persistent_bs, b, grid, step0, nsteps, st)
 }
 
-template <class S, bool ONE>
+template <class S, bool ONE, bool CUR>
 hipError_t capacity_one(const BatchConfig& c, int* blocks) {
-    if constexpr (sizeof(S) >= 4) {
-        if (c.stream_store) BATCH_BS(S, ONE, true, capacity_bs, blocks)
+    BATCH_NT(S, ONE, CUR, capacity_bs, blocks)
+}
+
+// F<S, ONE, CUR>(args...) for the two flags of kind
+#define BATCH_KIND(F, ...)                                                                         \
+    switch (kind & (BATCH_RATES_ONE | BATCH_CURVED)) {                                             \
+        case 0: return F<S, false, false>(__VA_ARGS__);                                            \
+        case BATCH_RATES_ONE: return F<S, true, false>(__VA_ARGS__);                               \
+        case BATCH_CURVED: return F<S, false, true>(__VA_ARGS__);                                  \
+        default: return F<S, true, true>(__VA_ARGS__);                                             \
     }
-    BATCH_BS(S, ONE, false, capacity_bs, blocks)
+
+template <class S>
+hipError_t step_s(int kind, const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
+    BATCH_KIND(step_one, b, c, step, monitor, st)
 }
 
 template <class S>
-hipError_t step_s(bool one, const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
-    return one ? step_one<S, true>(b, c, step, monitor, st) : step_one<S, false>(b, c, step, monitor, st);
+hipError_t capacity_s(int kind, const BatchConfig& c, int* blocks) {
+    BATCH_KIND(capacity_one, c, blocks)
 }
 
 template <class S>
-hipError_t capacity_s(bool one, const BatchConfig& c, int* blocks) {
-    return one ? capacity_one<S, true>(c, blocks) : capacity_one<S, false>(c, blocks);
-}
-
-template <class S>
-hipError_t persistent_s(bool one, const BatchArgs& b, const BatchConfig& c, int step0, int nsteps, hipStream_t st) {
+hipError_t persistent_s(int kind, const BatchArgs& b, const BatchConfig& c, int step0, int nsteps, hipStream_t st) {
     int grid = c.grid;
     int cap = 0;
-    hipError_t e = capacity_s<S>(one, c, &cap);
+    hipError_t e = capacity_s<S>(kind, c, &cap);
     if (e != hipSuccess) return e;
     // never more work-groups than fit at once: the barrier needs them all resident
     if (grid <= 0 || grid > cap) grid = cap;
     if (grid > b.nitems) grid = b.nitems;
     if (grid > MAX_PERSISTENT_GROUPS) grid = MAX_PERSISTENT_GROUPS;
-    return one ? persistent_one<S, true>(b, c, grid, step0, nsteps, st)
-               : persistent_one<S, false>(b, c, grid, step0, nsteps, st);
+    BATCH_KIND(persistent_one, b, c, grid, step0, nsteps, st)
 }
 
 }  // namespace
@@ -217,23 +221,23 @@ hipError_t persistent_s(bool one, const BatchArgs& b, const BatchConfig& c, int 
 #define LBM_BATCH_T __bf16
 #endif
 
-hipError_t launch_batch_step_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+hipError_t launch_batch_step_s(int storage, int kind, const BatchArgs& b, const BatchConfig& c, int step,
                                bool monitor, hipStream_t stream, std::integral_constant<int, LBM_BATCH_STORAGE>) {
     (void)storage;
-    return step_s<LBM_BATCH_T>(rates_one, b, c, step, monitor, stream);
+    return step_s<LBM_BATCH_T>(kind, b, c, step, monitor, stream);
 }
 
-hipError_t launch_batch_persistent_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+hipError_t launch_batch_persistent_s(int storage, int kind, const BatchArgs& b, const BatchConfig& c,
                                      int step0, int nsteps, hipStream_t stream,
                                      std::integral_constant<int, LBM_BATCH_STORAGE>) {
     (void)storage;
-    return persistent_s<LBM_BATCH_T>(rates_one, b, c, step0, nsteps, stream);
+    return persistent_s<LBM_BATCH_T>(kind, b, c, step0, nsteps, stream);
 }
 
-hipError_t batch_persistent_capacity_s(int storage, bool rates_one, const BatchConfig& c, int* blocks,
+hipError_t batch_persistent_capacity_s(int storage, int kind, const BatchConfig& c, int* blocks,
                                        std::integral_constant<int, LBM_BATCH_STORAGE>) {
     (void)storage;
-    return capacity_s<LBM_BATCH_T>(rates_one, c, blocks);
+    return capacity_s<LBM_BATCH_T>(kind, c, blocks);
 }
 
 }  // namespace lbm

@@ -132,6 +132,15 @@ int refresh_tables(lbm_batch* b) {
     return LBM_OK;
 }
 
+// Kernel flags of the batch: every domain CHM-MRT with free rates of one; some
+// domain with curved-wall records.
+int batch_kind(const lbm_batch* b) {
+    int kind = b->rates_one ? lbm::BATCH_RATES_ONE : 0;
+    for (const lbm_domain* d : b->doms)
+        if (!d->crec.empty()) kind |= lbm::BATCH_CURVED;
+    return kind;
+}
+
 // Enqueue nsteps (>= 1) steps of group g with the current configuration; the
 // last one accumulates the group's monitors.
 int enqueue_steps(lbm_batch* b, int g, int nsteps) {
@@ -140,35 +149,21 @@ int enqueue_steps(lbm_batch* b, int g, int nsteps) {
         // barrier epochs restart at 1 in every launch
         HIP_TRY(lbm::launch_fill_zero(a.barrier, lbm::BARRIER_WORDS * sizeof(unsigned), b->stream),
                 "barrier reset");
-        HIP_TRY(lbm::launch_batch_persistent(b->storage, b->rates_one, a, b->cfg, 0, nsteps - 1, b->stream),
+        HIP_TRY(lbm::launch_batch_persistent(b->storage, batch_kind(b), a, b->cfg, 0, nsteps - 1, b->stream),
                 "persistent batch kernel");
-        HIP_TRY(lbm::launch_batch_step(b->storage, b->rates_one, a, b->cfg, nsteps - 1, true, b->stream),
+        HIP_TRY(lbm::launch_batch_step(b->storage, batch_kind(b), a, b->cfg, nsteps - 1, true, b->stream),
                 "batch step kernel");
         return LBM_OK;
     }
-    for (int s = 0; s < nsteps; ++s) {
-        // curved-wall passes of the group's domains on the populations this step reads
-        for (int k = b->group_first[g]; k < b->group_first[g + 1]; ++k) {
-            const lbm_domain* d = b->doms[k];
-            if (d->pre.empty()) continue;
-            const lbm::StepArgs& da = b->args_host[k];
-            void* fin = const_cast<void*>((s & 1) ? (const void*)da.fout : da.fin);
-            const int rows = (int)((d->n + b->cfg.block - 1) / b->cfg.block);
-            HIP_TRY(lbm::launch_curved_pre(d->storage, fin, (const lbm::CurvedLink*)(d->dev + d->off_pre),
-                                           (int64_t)d->pre.size(),
-                                           s == nsteps - 1 ? da.partials + (size_t)rows * lbm::MON_WORDS : nullptr,
-                                           b->stream),
-                    "curved-wall pass");
-        }
-        HIP_TRY(lbm::launch_batch_step(b->storage, b->rates_one, a, b->cfg, s, s == nsteps - 1, b->stream),
+    for (int s = 0; s < nsteps; ++s)
+        HIP_TRY(lbm::launch_batch_step(b->storage, batch_kind(b), a, b->cfg, s, s == nsteps - 1, b->stream),
                 "batch step kernel");
-    }
     return LBM_OK;
 }
 
 int ensure_graphs(lbm_batch* b) {
     const int key[6] = {b->cfg.mode, b->cfg.block, b->cfg.stream_store, b->cfg.grid, b->cfg.group_mb,
-                        (int)b->rates_one};
+                        batch_kind(b)};
     const int ng = (int)b->group_first.size() - 1;
     if ((int)b->graphs.size() == ng && std::memcmp(key, b->graph_cfg, sizeof key) == 0) return LBM_OK;
     b->drop_graph();
@@ -227,16 +222,8 @@ int run_steps(lbm_batch* b, int nsteps) {
     return LBM_OK;
 }
 
-bool has_curved_pass(const lbm_batch* b) {
-    for (const lbm_domain* d : b->doms)
-        if (!d->pre.empty()) return true;
-    return false;
-}
-
 bool valid_config(const lbm_batch* b, const lbm::BatchConfig& c) {
     if (c.mode != 0 && c.mode != 1) return false;
-    // the persistent kernel has no place for the curved-wall pass between steps
-    if (c.mode == 1 && has_curved_pass(b)) return false;
     if (c.block != 128 && c.block != 256 && c.block != 512) return false;
     if (c.stream_store != 0 && c.stream_store != 1) return false;
     if (c.stream_store && b->storage >= LBM_F16S) return false;
@@ -351,7 +338,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
         if (!d->initialized) return fail(LBM_ESTATE, "every domain must be initialised");
     b->rates_one = true;
     for (lbm_domain* d : b->doms) b->rates_one = b->rates_one && d->rates_one();
-    const auto key = std::make_tuple(b->storage, (int)b->rates_one, (int)std::lround(std::log2((double)b->total_nodes)),
+    const auto key = std::make_tuple(b->storage, batch_kind(b), (int)std::lround(std::log2((double)b->total_nodes)),
                                      (int)b->doms.size());
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -368,7 +355,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
                 for (int ns : {0, 1}) {
                     if (ns && b->storage >= LBM_F16S) continue;
                     if (mode == 0) cands.push_back({0, block, ns, 0, group_mb});
-                    else if (!has_curved_pass(b)) {
+                    else {
                         cands.push_back({1, block, ns, 0, group_mb});
                         cands.push_back({1, block, ns, -2, group_mb});   // half of the resident capacity
                     }
@@ -383,7 +370,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
     for (lbm::BatchConfig c : cands) {
         if (c.grid == -2) {
             int cap = 0;
-            if (lbm::batch_persistent_capacity(b->storage, b->rates_one, c, &cap) != hipSuccess || cap < 2) continue;
+            if (lbm::batch_persistent_capacity(b->storage, batch_kind(b), c, &cap) != hipSuccess || cap < 2) continue;
             c.grid = cap / 2;
         }
         b->cfg = c;
@@ -437,18 +424,18 @@ namespace lbm {
         default: return hipErrorInvalidValue;                                         \
     }
 
-hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+hipError_t launch_batch_step(int storage, int kind, const BatchArgs& b, const BatchConfig& c, int step,
                              bool monitor, hipStream_t stream) {
-    LBM_BATCH_SWITCH(launch_batch_step_s, rates_one, b, c, step, monitor, stream)
+    LBM_BATCH_SWITCH(launch_batch_step_s, kind, b, c, step, monitor, stream)
 }
 
-hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+hipError_t launch_batch_persistent(int storage, int kind, const BatchArgs& b, const BatchConfig& c,
                                    int step0, int nsteps, hipStream_t stream) {
-    LBM_BATCH_SWITCH(launch_batch_persistent_s, rates_one, b, c, step0, nsteps, stream)
+    LBM_BATCH_SWITCH(launch_batch_persistent_s, kind, b, c, step0, nsteps, stream)
 }
 
-hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks) {
-    LBM_BATCH_SWITCH(batch_persistent_capacity_s, rates_one, c, blocks)
+hipError_t batch_persistent_capacity(int storage, int kind, const BatchConfig& c, int* blocks) {
+    LBM_BATCH_SWITCH(batch_persistent_capacity_s, kind, c, blocks)
 }
 
 #undef LBM_BATCH_SWITCH

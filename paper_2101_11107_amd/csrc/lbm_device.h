@@ -341,21 +341,22 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
     }
 }
 
-// Node with open-boundary, periodic-x or curved-wall links: explicit byte
-// offsets, then the open-boundary corrections with the additive terms prepared
-// by the previous step (or the initial state): inlet f_a = f*_abar + add,
-// outlet f_a = -f*_abar + add (evaluated in FP64, rounded once); then the
-// curved-wall blends.
+// Node with open-boundary or periodic-x links: explicit byte offsets, then the
+// open-boundary corrections with the additive terms prepared by the previous
+// step (or the initial state): inlet f_a = f*_abar + add, outlet
+// f_a = -f*_abar + add (evaluated in FP64, rounded once).  wall_force: add the
+// halfway wall force of the wall links to F (the curved-wall blend adds it
+// otherwise).
 template <class S, bool MON>
 __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a,
                                                const LBM_GLOBAL SpecialNode* __restrict__ sp,
                                                typename Traits<S>::T (&f)[27], double (&F)[3],
-                                               double& qin, double& qout) {
+                                               double& qin, double& qout, bool wall_force) {
     using T = typename Traits<S>::T;
 #pragma unroll
     for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin, sp->off[al]);
     const uint32_t wm = sp->wallmask, lm = sp->linkmask;
-    if (MON && wm) {
+    if (MON && wall_force && wm) {
 #pragma unroll
         for (int al = 0; al < 27; ++al) {
             if ((wm >> al) & 1u) {
@@ -386,35 +387,85 @@ __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict
             }
         }
     }
-    const uint32_t qm = sp->qmask;
-    if (qm) {
-        // curved walls (Eq. (9)-(10)): f_a = w0 f*_abar(x) + w1 f2 with the
-        // weights and the second value chosen on the host from the wall
-        // distance; the wall force is (f*_abar(x) + f_a) c_abar per link
-        // (momentum exchange).  Shifted populations blend the same way: the
-        // weights sum to one and w_a = w_abar.
-        // One direction at a time, with a scheduling barrier between them:
-        // this rare path must not raise the register count of the whole step
-        // (hoisting its loads together would).
-        int l = sp->link0 + __popc(lm);
-        const LBM_GLOBAL double* wq = (const LBM_GLOBAL double*)a.link_wq;
-        const LBM_GLOBAL uint32_t* off2 = (const LBM_GLOBAL uint32_t*)a.link_off2;
+}
+
+// Curved walls (Eq. (9)-(10)), after the gather: each wall link's
+// bounce-back value f[al] = f*_abar(x) becomes
+// w0 f*_abar(x) + (1 - w0) f2, with the weight record r of the link (the
+// layout is described at CREC_CHUNK): f2 = f[abar] = f*_abar(x + c_al), the
+// value pulled for direction abar, for r > 0 (q < 1/2), and the node's own
+// f*_al(x) for r < 0 (q >= 1/2).  A link whose q < 1/2 rule lacks its second
+// node has r = 1, so f[abar] is never read where it is itself a wall value.
+// The records of one direction of a wavefront are consecutive, so a lane finds
+// its record from the wavefront's ballot of that direction; directions without
+// a wall link in the wavefront are skipped.  The directions are taken in two
+// halves, each issuing its record and second-value loads together; the first
+// half's loads go out with the gather's.  With MON, the
+// wall force of each link, (f*_abar(x) + f_al(x, t+1)) c_abar in full
+// populations, is subtracted from F.
+template <class S, bool MON>
+__device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a, int i,
+                                             uint32_t own0, uint32_t wallmask, typename Traits<S>::T (&f)[27],
+                                             double (&F)[3]) {
+    using T = typename Traits<S>::T;
+    constexpr uint32_t SZ = sizeof(S);
+    // byte distance between the node's populations of consecutive directions
+    const uint32_t dstep = SZ == 2 ? (uint32_t)a.npad * SZ : (1u << pop_tile_shift(SZ)) * SZ;
+    const LBM_GLOBAL T* __restrict__ rec = (const LBM_GLOBAL T*)a.crec;
+    // the chunk of 64 nodes is the wavefront's (blocks are whole wavefronts)
+    const int chunk = __builtin_amdgcn_readfirstlane(i / CREC_CHUNK);
+    uint32_t cum = ((const LBM_GLOBAL uint32_t*)a.crec_base)[chunk];
+    T fx = T(0), fy = T(0), fz = T(0);
 #pragma unroll
-        for (int al = 0; al < 27; ++al) {
-            if ((qm >> al) & 1u) {
-                const T own = f[al];
-                const T v = (T)wq[2 * l] * own + (T)wq[2 * l + 1] * ldp<S>(fin, off2[l]);
-                f[al] = v;
-                if (MON) {
-                    const double s = (double)own + (double)v + 2.0 * wgt(al);
-                    F[0] -= s * cxo(al);
-                    F[1] -= s * cyo(al);
-                    F[2] -= s * czo(al);
+    for (int h = 0; h < 2; ++h) {
+        // a lane without the link keeps r = 1, f2 = 0: its blend returns
+        // f[al] unchanged, so the blend needs no per-lane test
+        T r[13], f2[13];
+        unsigned long long B[13];
+#pragma unroll
+        for (int k = 0; k < 13; ++k) {
+            const int al = 14 * h + k;
+            const bool wl = (wallmask >> al) & 1u;
+            B[k] = __ballot(wl);
+            r[k] = T(1);
+            f2[k] = T(0);
+            if (B[k] != 0ull) {
+                const uint32_t idx = __builtin_amdgcn_mbcnt_hi((uint32_t)(B[k] >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)B[k], cum));
+                cum += (uint32_t)__popcll(B[k]);
+                if (wl) {
+                    r[k] = rec[idx];
+                    f2[k] = ldp<S>(fin, own0 + (uint32_t)al * dstep);
                 }
-                ++l;
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
+#pragma unroll
+        for (int k = 0; k < 13; ++k) {
+            const int al = 14 * h + k;
+            if (B[k] == 0ull) continue;
+            const T own = f[al];
+            const bool hi = r[k] < T(0);
+            const T w0 = hi ? -r[k] : r[k];
+            const T v = w0 * own + (T(1) - w0) * (hi ? f2[k] : f[26 - al]);
+            f[al] = v;
+            if (MON && ((wallmask >> al) & 1u)) {
+                const T m = own + v + T(2) * (T)wgt(al);
+                if (cxo(al)) fx += cxo(al) > 0 ? m : -m;
+                if (cyo(al)) fy += cyo(al) > 0 ? m : -m;
+                if (czo(al)) fz += czo(al) > 0 ? m : -m;
+            }
+        }
+        if (h == 0) {
+            // the second half's loads stay behind the first half's blend, so
+            // the two halves never hold their loaded values at once
+#pragma unroll
+            for (int k = 0; k < 13; ++k) asm volatile("" : "+v"(f[k]) : : "memory");
+        }
+    }
+    if (MON) {
+        F[0] -= (double)fx;
+        F[1] -= (double)fy;
+        F[2] -= (double)fz;
     }
 }
 
@@ -561,8 +612,9 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
 // --- one block of a step ---------------------------------------------------------
 // Logical block lb of the domain (BS consecutive nodes).  Used by the
 // single-domain kernel and by the batched kernels, so a node's arithmetic is
-// the same in both.
-template <class S, bool MON, int FORM, bool PER, bool NT, int BS>
+// the same in both.  CURVED: blend the curved-wall links of ordinary nodes
+// (a domain without weight records skips it).
+template <class S, bool MON, int FORM, bool PER, bool NT, int BS, bool CURVED>
 __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
@@ -576,13 +628,21 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         double F[3] = {0.0, 0.0, 0.0}, qin = 0.0, qout = 0.0;
         const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
         const LBM_GLOBAL SpecialNode* sp = nullptr;
+        const bool curved = CURVED && a.crec != nullptr;
+        // byte offset of the node's own direction-0 population (curved walls)
+        const uint32_t own0 = CURVED ? pop_index((uint32_t)i, 0u, (uint32_t)a.npad, SZ) * SZ : 0u;
         if (!(w & SPECIAL_BIT)) {
-            gather_fast<S, PER, MON>(fin, a, i, w, f, wallmask);
+            gather_fast<S, PER, MON || CURVED>(fin, a, i, w, f, wallmask);
         } else {
             sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
-            gather_special<S, MON>(fin, a, sp, f, F, qin, qout);
+            // read before the gather's loads, so that using it waits for none of them
+            if (curved) wallmask = sp->wallmask;
+            gather_special<S, MON>(fin, a, sp, f, F, qin, qout, !curved);
         }
-        if (MON && wallmask) {
+        if (curved) {
+            // every wall link has a record (r = 1: halfway)
+            if (__ballot(wallmask != 0u)) curved_blend<S, MON>(fin, a, i, own0, wallmask, f, F);
+        } else if (MON && wallmask) {
             T fx = T(0), fy = T(0), fz = T(0);
 #pragma unroll
             for (int al = 0; al < 27; ++al) {

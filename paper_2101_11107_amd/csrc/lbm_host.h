@@ -51,13 +51,11 @@ struct lbm_domain {
     std::vector<int32_t> link_meta;        // [nlinks] type | alpha << 8
     std::vector<double> link_coef;         // [nlinks][LINK_COEFS]
     std::vector<int32_t> link_xyz;         // [nlinks][3] node coordinates of each link
-    std::vector<double> link_wq;           // [nlinks][2] curved-wall weights (0 for other links)
-    std::vector<uint32_t> link_off2;       // [nlinks] second value of a curved-wall link (element, then byte)
-    std::vector<int32_t> link_off2_plane;  // [nlinks] its plane (until the layout is fixed)
-    int64_t ncurved = 0;                   // curved-wall links on explicit-offset nodes
-    std::vector<lbm::CurvedLink> pre;      // curved-wall links of ordinary nodes (pass before each step)
-    std::vector<int32_t> pre_src_plane;    // plane of each second value (until the layout is fixed)
-    int pre_blocks = 0;                    // monitor rows of the pass
+    // curved-wall weights (signed w0, layout at lbm::CREC_CHUNK; empty for
+    // halfway walls) and the first record of each 64-node chunk
+    std::vector<double> crec;
+    std::vector<float> crec_f32;           // the same in FP32 (storage other than f64)
+    std::vector<uint32_t> crec_base;
     std::vector<int32_t> coords;           // [n][3]
     bool has_inlet_links = false;
     size_t nlinks() const { return link_meta.size(); }
@@ -75,7 +73,7 @@ struct lbm_domain {
     size_t dev_bytes = 0;
     size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
            off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0,
-           off_lwq = 0, off_loff2 = 0, off_probe = 0, off_pre = 0;
+           off_probe = 0, off_crec = 0, off_cbase = 0;
     size_t pop_bytes = 0;
 
     int cur = 0;

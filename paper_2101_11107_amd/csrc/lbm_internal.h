@@ -48,41 +48,36 @@ struct alignas(8) RowEntry {
     int32_t prefix;
 };
 
-// Record of a node with open-boundary, periodic-x or curved-wall links.
-// off[alpha] is the byte offset (from the population buffer) of the value it
-// pulls: the source node's alpha population for a fluid link, its own abar
-// population for a wall or open link (bounce-back).  Open links then get the
-// boundary correction: inlet f += add, outlet f = -f + add.  Curved-wall links
-// (Eq. (9)-(10)) blend that value with a second one: f = w0 f + w1 f2.  The
-// node's links are numbered from link0: its open links in increasing alpha,
-// then its curved-wall links in increasing alpha.
+// Record of a node with open-boundary or periodic-x links.  off[alpha] is the
+// byte offset (from the population buffer) of the value it pulls: the source
+// node's alpha population for a fluid link, its own abar population for a wall
+// or open link (bounce-back).  Open links then get the boundary correction:
+// inlet f += add, outlet f = -f + add.  The node's open links are numbered
+// from link0 in increasing alpha.  Its wall links (wallmask) are blended after
+// the gather like those of ordinary nodes when the domain has curved walls.
 struct alignas(16) SpecialNode {
     uint32_t off[27];
     int32_t node;          // fluid-node index
     int32_t link0;         // first link of this node
-    uint32_t wallmask;     // bit alpha: halfway bounce-back wall link
+    uint32_t wallmask;     // bit alpha: wall link
     uint32_t linkmask;     // bit alpha: open-boundary link
-    uint32_t qmask;        // bit alpha: curved-wall link
+    uint32_t reserved;
 };
 static_assert(sizeof(SpecialNode) == 128, "special node record is 128 bytes");
 
-enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3, LINK_WALL_Q = 4 };
+enum : int32_t { LINK_INLET = 2, LINK_OUTLET = 3 };
 
-// Curved-wall link of an ordinary node (Eq. (9)-(10)).  The population that
-// bounces back at a wall link, f*_abar(x) with abar = 26 - dir, is read by no
-// other node (its streaming destination is the wall), so a pass before the
-// step replaces it in place by w0 f*_abar(x) + w1 f2, which the bitmap path
-// then pulls as its ordinary bounce-back value.  dst, src2: byte offsets
-// (from the population buffer) of f*_abar(x) and f2; dir: the incoming
-// direction of the link.
-struct alignas(8) CurvedLink {
-    uint32_t dst;
-    uint32_t src2;
-    int32_t dir;
-    int32_t pad;
-    double w0, w1;
-};
-static_assert(sizeof(CurvedLink) == 32, "curved-wall record is 32 bytes");
+// Curved-wall weights (Eq. (9)-(10)), blended into the step after the
+// gather.  One weight r per wall link of a node, stored in the population's
+// arithmetic type: grouped by chunk of 64
+// consecutive nodes (one wavefront), inside a chunk by incoming direction
+// alpha, inside a direction by node; crec_base[chunk] is the chunk's first
+// record.  |r| = w0 is the weight of the bounce-back value f*_abar(x) and
+// 1 - w0 that of the second value: for r > 0 (q < 1/2) f*_abar(x + c_alpha),
+// which the node pulls for direction abar anyway; for r < 0 (q >= 1/2) the
+// node's own f*_alpha(x).  Wall links without a distance have r = 1 (halfway
+// bounce-back).
+constexpr int CREC_CHUNK = 64;
 
 // Per open-boundary link: meta = type | alpha << 8; coef = (a0, a1re, a1im,
 // k1, k3, k5): the inlet speed at the link midpoint is
@@ -101,8 +96,8 @@ struct StepArgs {
     const int32_t* link_meta;    // [nlinks]
     const double* link_coef;     // [nlinks][LINK_COEFS]
     double* link_add;            // [nlinks]
-    const double* link_wq;       // [nlinks][2] curved-wall weights (w0, w1)
-    const uint32_t* link_off2;   // [nlinks] byte offset of a curved-wall link's second value
+    const void* crec;            // curved-wall weights, or null (halfway walls)
+    const uint32_t* crec_base;   // [npad / CREC_CHUNK] first record of each 64-node chunk
     int64_t* tcount;             // [2] time counters (read slot tin, write slot tin ^ 1)
     double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials
@@ -130,6 +125,7 @@ struct StepVariant {
     bool periodic_yz;    // a periodic y or z axis (node words hold x, y, z)
     bool stream_store;   // non-temporal population stores (working set beyond the Infinity Cache)
     bool srt2;           // the SRT comparator instead of CHM-MRT
+    bool curved;         // curved-wall weights (crec set)
 };
 
 // Several domains stepped by one launch.  Work item k of the launch is block
@@ -159,10 +155,11 @@ struct BatchConfig {
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream);
-// Curved-wall pass before a step on the populations `fin` it will read;
-// partials: nullptr, or the monitor rows of its wall-force correction.
-hipError_t launch_curved_pre(int storage, void* fin, const CurvedLink* links, int64_t n, double* partials,
-                             hipStream_t stream);
+// The step launcher of one storage type (lbm_step.hip, one translation unit each).
+hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 0>);
+hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 1>);
+hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 2>);
+hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 3>);
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream);
 hipError_t launch_moments(int storage, const StepArgs& a, double* rho, double* u, double* avg,
@@ -172,23 +169,26 @@ hipError_t launch_monitor_finalize(const double* partials, int nblocks, double* 
                                    hipStream_t stream);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 
-// Batched launchers (lbm_batch.hip).  step: the step index within the launch
-// sequence (its parity selects the buffers); monitor: accumulate monitors.
-hipError_t launch_batch_step(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c, int step,
+// Batched launchers (lbm_batch.hip).  kind: BATCH_RATES_ONE when every domain
+// is CHM-MRT with free rates of one, | BATCH_CURVED when a domain has
+// curved-wall records; step: the step index within the launch sequence (its
+// parity selects the buffers); monitor: accumulate monitors.
+enum : int { BATCH_RATES_ONE = 1, BATCH_CURVED = 2 };
+hipError_t launch_batch_step(int storage, int kind, const BatchArgs& b, const BatchConfig& c, int step,
                              bool monitor, hipStream_t stream);
-hipError_t launch_batch_persistent(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,
+hipError_t launch_batch_persistent(int storage, int kind, const BatchArgs& b, const BatchConfig& c,
                                    int step0, int nsteps, hipStream_t stream);
 // Work-groups of the persistent kernel that fit on the device at once.
-hipError_t batch_persistent_capacity(int storage, bool rates_one, const BatchConfig& c, int* blocks);
+hipError_t batch_persistent_capacity(int storage, int kind, const BatchConfig& c, int* blocks);
 // One definition per storage type, each in its own translation unit; the
 // functions above dispatch to them.
 #define LBM_BATCH_DECL(K)                                                                                  \
-    hipError_t launch_batch_step_s(int storage, bool rates_one, const BatchArgs& b, const BatchConfig& c,   \
+    hipError_t launch_batch_step_s(int storage, int kind, const BatchArgs& b, const BatchConfig& c,   \
                                    int step, bool monitor, hipStream_t stream, std::integral_constant<int, K>); \
-    hipError_t launch_batch_persistent_s(int storage, bool rates_one, const BatchArgs& b,                  \
+    hipError_t launch_batch_persistent_s(int storage, int kind, const BatchArgs& b,                  \
                                          const BatchConfig& c, int step0, int nsteps, hipStream_t stream,   \
                                          std::integral_constant<int, K>);                                   \
-    hipError_t batch_persistent_capacity_s(int storage, bool rates_one, const BatchConfig& c, int* blocks,  \
+    hipError_t batch_persistent_capacity_s(int storage, int kind, const BatchConfig& c, int* blocks,  \
                                            std::integral_constant<int, K>);
 LBM_BATCH_DECL(0)
 LBM_BATCH_DECL(1)

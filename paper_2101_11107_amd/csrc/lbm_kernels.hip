@@ -1,21 +1,10 @@
 // Single-domain HIP kernels of the lattice Boltzmann library (gfx950) and
-// their launchers: the step, initialisation, moments, population read-out,
-// monitor reduction and buffer clearing.
+// their launchers: initialisation, moments, population read-out, monitor
+// reduction and buffer clearing (the step kernel is in lbm_step.hip).
 #include "lbm_device.h"
 
 namespace lbm {
 namespace {
-
-// One step over one domain.  XCD-aware order: hardware work-group b runs on
-// XCD (b % 8); each XCD gets a contiguous range of the node list, so
-// neighbouring rows share its L2.
-template <class S, bool MON, int FORM, bool PER, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
-    const int hb = blockIdx.x;
-    const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
-    if (lb >= a.nblocks) return;
-    step_block<S, MON, FORM, PER, NT, BLOCK>(a, lb);
-}
 
 // Initial state: f(0) = f_eq(rho, u), then the first collision (written to
 // fout), and the open-link terms for the first step.
@@ -131,78 +120,10 @@ __global__ __launch_bounds__(BLOCK) void k_mon_final(const double* __restrict__ 
     if (threadIdx.x < 9) out[threadIdx.x] = sh[0][threadIdx.x];
 }
 
-// One curved-wall link per thread: f*_abar(x) <- w0 f*_abar(x) + w1 f2 (the
-// links of one launch write distinct places and read no place another writes;
-// the host keeps nodes where that would fail on the explicit-offset path).
-// With MON, the wall-force correction of the link: the step counts
-// 2 (f_new + w) c_abar for a wall link, momentum exchange wants
-// (f*_abar + f_new + 2 w) c_abar, so this adds (f*_abar - f_new) c_abar.
-template <class S, bool MON>
-__global__ __launch_bounds__(BLOCK) void k_curved_pre(char* __restrict__ fin, const CurvedLink* __restrict__ links,
-                                                      int64_t n, double* __restrict__ partials) {
-    using T = typename Traits<S>::T;
-    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (k < n) {
-        const LBM_GLOBAL CurvedLink* r = (const LBM_GLOBAL CurvedLink*)links + k;
-        LBM_GLOBAL char* base = (LBM_GLOBAL char*)fin;
-        const uint32_t dst = r->dst;
-        const T own = ldp<S>(base, dst);
-        const T v = (T)r->w0 * own + (T)r->w1 * ldp<S>(base, r->src2);
-        stp<S>(base, dst, v);
-        if (MON) {
-            const int al = r->dir;
-            const double d = (double)own - (double)v;   // c_abar = -c_al
-            mon[4] = -d * (double)(al % 3 - 1);
-            mon[5] = -d * (double)((al / 3) % 3 - 1);
-            mon[6] = -d * (double)(al / 9 - 1);
-        }
-    }
-    if (MON) block_monitor<BLOCK>(mon, partials + (size_t)blockIdx.x * MON_WORDS);
-}
-
 __global__ void k_fill_zero(uint32_t* p, size_t nwords) {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords;
          k += (size_t)gridDim.x * blockDim.x)
         p[k] = 0u;
-}
-
-// FP32 steps of domains beyond the Infinity Cache run six work-groups per CU
-// instead of the eight their registers allow: each work-group then lives a
-// shorter time, so the tail at the end of a step drains sooner (measured 1 %
-// faster at 512^3; the 2-byte forms lose with fewer waves, FP64 is limited to
-// five by its registers).  The cap is set through the dynamic LDS size:
-// 6 x (26000 B + the monitor's static LDS) fits the CU's 160 KiB, 7 x does not.
-constexpr unsigned STEP_LDS_SIX_PER_CU = 26000;
-
-template <class S, bool MON, int FORM, bool NT>
-hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
-    const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
-    const unsigned lds = (NT && sizeof(S) == 4) ? STEP_LDS_SIX_PER_CU : 0u;
-    if (per) hipLaunchKernelGGL((k_step<S, MON, FORM, true, NT>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_step<S, MON, FORM, false, NT>), grid, block, lds, st, a);
-    return hipGetLastError();
-}
-
-template <class S, bool MON, bool NT>
-hipError_t step_form(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if (v.srt2) return step_per<S, MON, 2, NT>(a, v.periodic_yz, st);
-    return v.rates_one ? step_per<S, MON, 1, NT>(a, v.periodic_yz, st) : step_per<S, MON, 0, NT>(a, v.periodic_yz, st);
-}
-
-template <class S, bool NT>
-hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
-    return v.monitor ? step_form<S, true, NT>(a, v, st) : step_form<S, false, NT>(a, v, st);
-}
-
-// Streaming stores only pay for 4- and 8-byte populations (measured); the
-// 2-byte forms always store normally.
-template <class S>
-hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if constexpr (sizeof(S) >= 4) {
-        if (v.stream_store) return step_nt<S, true>(a, v, st);
-    }
-    return step_nt<S, false>(a, v, st);
 }
 
 template <class S>
@@ -235,22 +156,14 @@ hipError_t readpop_t(const StepArgs& a, double* out, hipStream_t st) {
         default: return hipErrorInvalidValue;                           \
     }
 
-template <class S>
-hipError_t curved_pre_t(void* fin, const CurvedLink* links, int64_t n, double* partials, hipStream_t st) {
-    const dim3 grid((unsigned)((n + BLOCK - 1) / BLOCK)), block(BLOCK);
-    if (partials) hipLaunchKernelGGL((k_curved_pre<S, true>), grid, block, 0, st, (char*)fin, links, n, partials);
-    else hipLaunchKernelGGL((k_curved_pre<S, false>), grid, block, 0, st, (char*)fin, links, n, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_curved_pre(int storage, void* fin, const CurvedLink* links, int64_t n, double* partials,
-                             hipStream_t stream) {
-    if (n <= 0) return hipSuccess;
-    LBM_DISPATCH(storage, curved_pre_t, fin, links, n, partials, stream);
-}
-
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream) {
-    LBM_DISPATCH(storage, step_t, a, v, stream);
+    switch (storage) {
+        case 0: return launch_step_s(a, v, stream, std::integral_constant<int, 0>());
+        case 1: return launch_step_s(a, v, stream, std::integral_constant<int, 1>());
+        case 2: return launch_step_s(a, v, stream, std::integral_constant<int, 2>());
+        case 3: return launch_step_s(a, v, stream, std::integral_constant<int, 3>());
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,

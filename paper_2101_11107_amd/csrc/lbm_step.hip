@@ -1,0 +1,85 @@
+// Single-domain step kernel (gfx950) and its launcher, compiled once per
+// storage type (LBM_STEP_STORAGE = 0 f64, 1 f32, 2 f16s, 3 bf16s) so the
+// variants compile in parallel.
+#include "lbm_device.h"
+
+#include <type_traits>
+
+namespace lbm {
+namespace {
+
+// One step over one domain.  XCD-aware order: hardware work-group b runs on
+// XCD (b % 8); each XCD gets a contiguous range of the node list, so
+// neighbouring rows share its L2.
+template <class S, bool MON, int FORM, bool PER, bool NT, bool CURVED>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
+    const int hb = blockIdx.x;
+    const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
+    if (lb >= a.nblocks) return;
+    step_block<S, MON, FORM, PER, NT, BLOCK, CURVED>(a, lb);
+}
+
+// FP32 steps of domains beyond the Infinity Cache run six work-groups per CU
+// instead of the eight their registers allow: each work-group then lives a
+// shorter time, so the tail at the end of a step drains sooner (measured 1 %
+// faster at 512^3; the 2-byte forms lose with fewer waves, FP64 is limited to
+// five by its registers).  The cap is set through the dynamic LDS size:
+// 6 x (26000 B + the monitor's static LDS) fits the CU's 160 KiB, 7 x does not.
+constexpr unsigned STEP_LDS_SIX_PER_CU = 26000;
+
+template <class S, bool MON, int FORM, bool NT, bool CURVED>
+hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
+    const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
+    const unsigned lds = (NT && sizeof(S) == 4) ? STEP_LDS_SIX_PER_CU : 0u;
+    if (per) hipLaunchKernelGGL((k_step<S, MON, FORM, true, NT, CURVED>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_step<S, MON, FORM, false, NT, CURVED>), grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
+template <class S, bool MON, bool NT, bool CURVED>
+hipError_t step_form(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.srt2) return step_per<S, MON, 2, NT, CURVED>(a, v.periodic_yz, st);
+    return v.rates_one ? step_per<S, MON, 1, NT, CURVED>(a, v.periodic_yz, st)
+                       : step_per<S, MON, 0, NT, CURVED>(a, v.periodic_yz, st);
+}
+
+template <class S, bool NT, bool CURVED>
+hipError_t step_mon(const StepArgs& a, StepVariant v, hipStream_t st) {
+    return v.monitor ? step_form<S, true, NT, CURVED>(a, v, st) : step_form<S, false, NT, CURVED>(a, v, st);
+}
+
+template <class S, bool NT>
+hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
+    return v.curved ? step_mon<S, NT, true>(a, v, st) : step_mon<S, NT, false>(a, v, st);
+}
+
+// Streaming stores only pay for 4- and 8-byte populations (measured); the
+// 2-byte forms always store normally.
+template <class S>
+hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if constexpr (sizeof(S) >= 4) {
+        if (v.stream_store) return step_nt<S, true>(a, v, st);
+    }
+    return step_nt<S, false>(a, v, st);
+}
+
+}  // namespace
+
+#if !defined(LBM_STEP_STORAGE)
+#error "compile with -DLBM_STEP_STORAGE=0..3"
+#elif LBM_STEP_STORAGE == 0
+#define LBM_STEP_T double
+#elif LBM_STEP_STORAGE == 1
+#define LBM_STEP_T float
+#elif LBM_STEP_STORAGE == 2
+#define LBM_STEP_T _Float16
+#else
+#define LBM_STEP_T __bf16
+#endif
+
+hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream,
+                         std::integral_constant<int, LBM_STEP_STORAGE>) {
+    return step_t<LBM_STEP_T>(a, v, stream);
+}
+
+}  // namespace lbm

@@ -31,7 +31,7 @@ def kernel_source_hash() -> str:
     """Hash of the step kernel's sources (the bench accepts a summary only
     when it matches)."""
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
+    for name in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h"):
         with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -74,28 +74,31 @@ def counter(run_dir: str, name: str) -> tuple:
     return copy, steps
 
 
-def fluid_nodes(trace_dir: str) -> int:
-    """Fluid-node count from the bench result line captured beside the run."""
+def fluid_nodes(trace_dir: str) -> tuple:
+    """(fluid nodes, curved wall links) from the bench result line captured
+    beside the run."""
     with open(os.path.join(os.path.dirname(trace_dir.rstrip("/")), "trace.log")) as fh:
         for line in fh:
             if line.startswith("{"):
-                return int(json.loads(line)["config"]["fluid_nodes"])
+                cfg = json.loads(line)["config"]
+                return int(cfg["fluid_nodes"]), int(cfg.get("wall_links", 0))
     raise ValueError("no bench result line in trace.log")
 
 
 def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str) -> str:
     trace, fetch, write = (os.path.join(folder, k) for k in ("trace", "fetch", "write"))
     rows, avg_us, calls = step_stats(trace)
-    n = fluid_nodes(trace)
+    n, links = fluid_nodes(trace)
     moved_kib = copy_mib * 1024.0                     # the copy reads and writes this much
     fc, fs = counter(fetch, "FETCH_SIZE")
     wc, ws = counter(write, "WRITE_SIZE")
     f_scale, w_scale = moved_kib / fc, moved_kib / wc
     fetch_b = f_scale * sum(fs) / len(fs) * 1024.0
     write_b = w_scale * sum(ws) / len(ws) * 1024.0
-    alg = 54 * POP_BYTES[storage] * n
+    rec = 8 if storage == "f64" else 4
+    alg = 54 * POP_BYTES[storage] * n + rec * links
     out = [f"# rocprofv3 summary: D3Q27 CHM-MRT step kernel (k_step), {storage} storage, workload {workload} "
-           f"({n} fluid nodes)",
+           f"({n} fluid nodes{f', {links} curved wall links' if links else ''})",
            f"# kernel trace command : rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run -- {cmd}",
            f"# FETCH_SIZE command   : rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {cmd}",
            f"# WRITE_SIZE command   : rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {cmd}",
@@ -113,7 +116,8 @@ def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str)
             f"-> scale {f_scale:.3f} / {w_scale:.3f}",
             f"#   step: FETCH_SIZE {sum(fs) / len(fs):.1f} KiB, WRITE_SIZE {sum(ws) / len(ws):.1f} KiB per dispatch "
             f"(n={len(fs)}, {len(ws)})",
-            f"#   algorithmic bytes per launch (54 populations x {POP_BYTES[storage]} B x nodes): {alg}",
+            f"#   algorithmic bytes per launch (54 populations x {POP_BYTES[storage]} B x nodes"
+            f"{f' + {rec} B weight x wall links' if links else ''}): {alg}",
             f"#   measured / algorithmic: read {fetch_b / (alg / 2):.3f}, write {write_b / (alg / 2):.3f}, "
             f"total {(fetch_b + write_b) / alg:.3f}",
             f"#   roofline: {alg / (avg_us * 1e-6) / 1e9:.1f} GB/s algorithmic on the kernel time "

@@ -20,14 +20,20 @@ def test_roofline_uses_algorithmic_bytes():
     assert r["peak"] == 8000.0 and r["unit"] == "GB/s" and r["bound"] == "hbm"
     assert abs(r["frac"] - 0.027) < 1e-12
     assert bench.roofline(10, 1.0, "f16s", None)["algorithmic_bytes_per_launch"] == 54 * 2 * 10
+    # curved walls add one weight per wall link (8 B with FP64 storage, 4 B otherwise)
+    assert bench.roofline(10, 1.0, "f16s", None, 7)["algorithmic_bytes_per_launch"] == 54 * 2 * 10 + 4 * 7
+    assert bench.roofline(10, 1.0, "f64", None, 7)["algorithmic_bytes_per_launch"] == 54 * 8 * 10 + 8 * 7
 
 
 def test_committed_profiles_match_current_kernel_source():
     import bench
-    for st, wl in (("f32", "aneurysm512"), ("f32", "aneurysm256"), ("f16s", "aneurysm512")):
+    for st, wl in (("f32", "aneurysm512"), ("f32", "aneurysm256"), ("f16s", "aneurysm512"), ("f64", "aneurysm512"),
+                   ("bf16s", "aneurysm512"), ("f32", "aneurysm512_curved")):
         prof = bench.read_profile(st, wl)
         assert prof, f"profiles/traffic_k_step_{st}_{wl}.txt is missing or was taken on another kernel source"
-        alg = 54 * bench.POP_BYTES[st] * (2121645 if wl == "aneurysm512" else 262221)
+        alg = 54 * bench.POP_BYTES[st] * (262221 if wl == "aneurysm256" else 2121645)
+        if wl.endswith("_curved"):
+            alg += 4 * 1457610          # FP32 weight per wall link of the 512^3 geometry
         assert int(prof["algorithmic_bytes_per_launch"]) == alg
         assert 1.0 <= float(prof["hbm_bytes_per_launch"]) / alg < 1.3
         assert float(prof["avg_step_kernel_us"]) > 0

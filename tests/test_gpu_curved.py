@@ -53,6 +53,21 @@ def test_random_wall_distances_f32_population_parity(seed):
     assert np.max(np.abs(f - ref)) < 1e-5 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("storage,tol", [("f16s", 1e-3), ("bf16s", 8e-3)])
+@pytest.mark.parametrize("seed", [0, 3])
+def test_random_wall_distances_reduced_storage(storage, tol, seed):
+    """The 2-byte storage forms blend in FP32 with FP32 weights and round the
+    result once on store: populations within the form's bound (1e-3 f16s,
+    8e-3 bf16s, of the largest population) after 20 steps."""
+    print(f"case curved tiny{seed} {storage}", flush=True)
+    case = synth.random_tiny_case(seed, nx=11, ny=9, nz=8)
+    wq = _random_q(case, seed)
+    dom, f = gpu_run(case, storage, 20, wall_q=wq)
+    dom.close()
+    _, ref, _, _ = oracle_post(case, 20, wall_q=wq)
+    assert np.max(np.abs(f - ref)) < tol * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_half_distance_equals_halfway_bounce_back_bitwise(storage):
     """q = 1/2 on every wall link through the curved-wall path gives the
