@@ -450,8 +450,9 @@ def main():
                      "seconds_high": rs["seconds_high"], "seconds_low": rs["seconds_low"],
                      "cost_ratio": rs["cost_ratio"]})
         note(f"resolution study: SI {also[-1]['plane_similarity_index']}, cost ratio {rs['cost_ratio']}")
-        also.append(batch_bench(torch, lbm, 480))
-        note(f"batch: {also[-1]['batched_mlups']:.1f} MLUPS batched")
+        for st in ("f16s", "f32"):
+            also.append(batch_bench(torch, lbm, 480, storage=st))
+            note(f"batch {st}: {also[-1]['batched_mlups']:.1f} MLUPS batched, frac {also[-1]['roofline_frac']}")
         if not args.no_corrector:
             also.append(corrector_bench())
             note("corrector protocol done")

@@ -296,8 +296,9 @@ int lbm_batch_attach_device(lbm_batch* batch, void* dev_ptr, size_t bytes);
  * device-wide barrier between steps), work-group size (128, 256 or 512),
  * streaming stores (0/1; 4- and 8-byte storage only), persistent grid (0 =
  * every work-group that fits at once), group budget in MiB (0: all domains
- * form one group; otherwise consecutive domains are grouped while their
- * population working set stays within the budget, and each group runs all
+ * form one group; otherwise the domains are split into as many groups of
+ * consecutive domains as the total population working set divided by the
+ * budget, rounded up, with near-equal working sets, and each group runs all
  * requested steps before the next, which keeps it in the device cache) }.
  * EINVAL for other values. */
 int lbm_batch_config(const lbm_batch* batch, int cfg[5]);

@@ -117,11 +117,17 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs b, int step0,
     }
 }
 
+// FP32 with streaming stores caps the resident work-groups of 256 threads at
+// six per CU through the dynamic LDS size, as the single-domain step does
+// (6 x 26000 B fits the CU's 160 KiB, 7 x does not).
+constexpr unsigned BATCH_LDS_SIX_PER_CU = 26000;
+
 template <class S, bool ONE, bool NT, int BS, bool CUR>
 hipError_t step_bs(const BatchArgs& b, int step, bool monitor, hipStream_t st) {
     const dim3 grid(8 * b.items_per_xcd), block(BS);
-    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS, CUR>), grid, block, 0, st, b, step);
-    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS, CUR>), grid, block, 0, st, b, step);
+    const unsigned lds = (NT && sizeof(S) == 4 && BS == 256) ? BATCH_LDS_SIX_PER_CU : 0u;
+    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS, CUR>), grid, block, lds, st, b, step);
+    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS, CUR>), grid, block, lds, st, b, step);
     return hipGetLastError();
 }
 

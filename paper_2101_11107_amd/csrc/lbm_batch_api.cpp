@@ -92,18 +92,26 @@ int refresh_tables(lbm_batch* b) {
     }
     if (!stale) return LBM_OK;
     const int bs = b->cfg.block;
-    const size_t budget = b->cfg.group_mb > 0 ? ((size_t)b->cfg.group_mb << 20) : SIZE_MAX;
+    // Groups of consecutive domains: as many as the working-set budget asks
+    // for (both population buffers of each domain), with boundaries at the
+    // domain edges closest to equal shares, so no group is left small (a
+    // small launch runs below the bandwidth of a large one).
+    const size_t nd = b->doms.size();
+    std::vector<double> cum(nd + 1, 0.0);
+    for (size_t k = 0; k < nd; ++k) cum[k + 1] = cum[k] + 2.0 * (double)b->doms[k]->pop_bytes;
+    const double budget = b->cfg.group_mb > 0 ? (double)((size_t)b->cfg.group_mb << 20) : 0.0;
+    const size_t ngroups = budget > 0.0 ? std::min(nd, (size_t)std::ceil(cum[nd] / budget)) : 1;
     b->group_first.assign(1, 0);
-    size_t acc = 0;
-    for (size_t k = 0; k < b->doms.size(); ++k) {
-        const size_t ws = 2 * b->doms[k]->pop_bytes;
-        if (acc > 0 && acc + ws > budget) {
-            b->group_first.push_back((int)k);
-            acc = 0;
-        }
-        acc += ws;
+    for (size_t g = 1; g < ngroups; ++g) {
+        const double target = cum[nd] * (double)g / (double)ngroups;
+        size_t k = (size_t)b->group_first.back() + 1;
+        while (k < nd && cum[k] < target) ++k;
+        if (k > (size_t)b->group_first.back() + 1 && target - cum[k - 1] < cum[k] - target) --k;
+        // keep at least one domain for each group still to come
+        k = std::min(k, nd - (ngroups - g));
+        b->group_first.push_back((int)k);
     }
-    b->group_first.push_back((int)b->doms.size());
+    b->group_first.push_back((int)nd);
     const int ng = (int)b->group_first.size() - 1;
     b->args_host.resize(b->doms.size());
     b->built_parity.resize(b->doms.size());

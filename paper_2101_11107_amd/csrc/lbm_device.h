@@ -77,6 +77,23 @@ __device__ __forceinline__ void stp(LBM_GLOBAL char* __restrict__ base, uint32_t
     else *(LBM_GLOBAL S*)(base + off) = Traits<S>::store(v);
 }
 
+// Byte offsets of the population layout split into a part shared by the
+// directions and a part shared by the nodes: population a of node n sits at
+// node_off(n) + plane_off(a).  Planes [27][npad] for 2-byte storage; tiles of
+// T nodes with their 27 directions as runs of T values otherwise (pop_index).
+// The direction part is uniform, so the kernels add it to the buffer's base
+// (scalar arithmetic) and keep one per-lane offset for every direction.
+template <class S>
+__device__ __forceinline__ uint32_t node_off(uint32_t n) {
+    constexpr uint32_t SZ = sizeof(S);
+    return SZ == 2 ? n * SZ : pop_index(n, 0u, 0u, SZ) * SZ;
+}
+template <class S>
+__device__ __forceinline__ uint32_t plane_off(int al, uint32_t npad) {
+    constexpr uint32_t SZ = sizeof(S);
+    return SZ == 2 ? (uint32_t)al * npad * SZ : (uint32_t)al * ((1u << pop_tile_shift(SZ)) * SZ);
+}
+
 // Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
 __device__ inline double feq1(int a, double rho, const double u[3]) {
     double r = rho;
@@ -317,6 +334,8 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
         rp[q] = *(const LBM_GLOBAL RowWord2*)(rt + e * 8u);
     }
     __builtin_amdgcn_sched_barrier(0);
+    const uint32_t npad = (uint32_t)a.npad;
+    const uint32_t own = node_off<S>((uint32_t)i);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ky = q % 3, kz = q / 3;
@@ -328,14 +347,19 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
             const int al = 9 * kz + 3 * ky + kx;
             const int k = 2 - kx;              // bit of the source cell x - cx
             if (al == 13) {
-                f[al] = ldp<S>(fin, pop_index((uint32_t)i, 13u, (uint32_t)a.npad, SZ) * SZ);
+                f[al] = ldp<S>(fin + plane_off<S>(13, npad), own);
                 continue;
             }
             const bool fl = (win >> k) & 1u;
             const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
-            const uint32_t off = fl ? pop_index((uint32_t)src, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ
-                                    : pop_index((uint32_t)i, (uint32_t)(26 - al), (uint32_t)a.npad, SZ) * SZ;
-            f[al] = ldp<S>(fin, off);
+            // pulled value: plane al of the source node; bounce-back: plane
+            // abar of this node.  Both offsets are taken from the lower of the
+            // two planes, so that neither is negative.
+            const int lo = al < 13 ? al : 26 - al;
+            const uint32_t gap = plane_off<S>(26 - 2 * lo, npad);     // plane(hi) - plane(lo)
+            const uint32_t pull = node_off<S>((uint32_t)src) + (al > 13 ? gap : 0u);
+            const uint32_t bounce = own + (al < 13 ? gap : 0u);
+            f[al] = ldp<S>(fin + plane_off<S>(lo, npad), fl ? pull : bounce);
             if (WALLS && !fl) wallmask |= 1u << al;
         }
     }
@@ -409,8 +433,6 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
                                              double (&F)[3]) {
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
-    // byte distance between the node's populations of consecutive directions
-    const uint32_t dstep = SZ == 2 ? (uint32_t)a.npad * SZ : (1u << pop_tile_shift(SZ)) * SZ;
     const LBM_GLOBAL T* __restrict__ rec = (const LBM_GLOBAL T*)a.crec;
     // the chunk of 64 nodes is the wavefront's (blocks are whole wavefronts)
     const int chunk = __builtin_amdgcn_readfirstlane(i / CREC_CHUNK);
@@ -435,7 +457,7 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
                 cum += (uint32_t)__popcll(B[k]);
                 if (wl) {
                     r[k] = rec[idx];
-                    f2[k] = ldp<S>(fin, own0 + (uint32_t)al * dstep);
+                    f2[k] = ldp<S>(fin + plane_off<S>(al, (uint32_t)a.npad), own0);
                 }
             }
         }
@@ -448,8 +470,11 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
             const T w0 = hi ? -r[k] : r[k];
             const T v = w0 * own + (T(1) - w0) * (hi ? f2[k] : f[26 - al]);
             f[al] = v;
-            if (MON && ((wallmask >> al) & 1u)) {
-                const T m = own + v + T(2) * (T)wgt(al);
+            if (MON) {
+                // this lane's bit of the ballot (not of wallmask: reusing that
+                // test would keep one register per direction alive across the loads)
+                const T on = (T)(uint32_t)((B[k] >> __lane_id()) & 1ull);
+                const T m = on * (own + v + T(2) * (T)wgt(al));
                 if (cxo(al)) fx += cxo(al) > 0 ? m : -m;
                 if (cyo(al)) fy += cyo(al) > 0 ? m : -m;
                 if (czo(al)) fz += czo(al) > 0 ? m : -m;
@@ -629,8 +654,8 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
         const LBM_GLOBAL SpecialNode* sp = nullptr;
         const bool curved = CURVED && a.crec != nullptr;
-        // byte offset of the node's own direction-0 population (curved walls)
-        const uint32_t own0 = CURVED ? pop_index((uint32_t)i, 0u, (uint32_t)a.npad, SZ) * SZ : 0u;
+        // the node's own population offset without its direction part (curved walls)
+        const uint32_t own0 = CURVED ? node_off<S>((uint32_t)i) : 0u;
         if (!(w & SPECIAL_BIT)) {
             gather_fast<S, PER, MON || CURVED>(fin, a, i, w, f, wallmask);
         } else {
@@ -696,7 +721,7 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             mon[8] = qout;
         }
 #pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S, NT>(fout, pop_index((uint32_t)i, (uint32_t)al, (uint32_t)a.npad, SZ) * SZ, f[al]);
+        for (int al = 0; al < 27; ++al) stp<S, NT>(fout + plane_off<S>(al, (uint32_t)a.npad), node_off<S>((uint32_t)i), f[al]);
         // after the stores, so the populations are no longer live
         if (sp != nullptr && sp->linkmask != 0u)
             update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);
