@@ -1,10 +1,10 @@
 // Device code of the D3Q27 CHM-MRT step shared by the single-domain kernels
-// (lbm_kernels.hip) and the batched kernels (lbm_batch.hip).
+// (lbm_step.hip) and the batched kernels (lbm_batch.hip).
 //
 // One fused pull-scheme update per fluid node (Eq. (1)): gather the 27
 // incoming post-collision populations of the previous step from the
-// population buffer (pop_index layout: 256-byte runs of one direction, or one
-// plane per direction for 2-byte storage; halfway bounce-back for wall links,
+// population buffer (pop_index layout: 256-byte runs of one direction per
+// tile of nodes; halfway bounce-back for wall links,
 // Eq. (9) at q = 1/2; inlet/outlet rules for open links), form rho and j
 // (Eqs. (4)-(5)),
 // apply the central Hermite moment collision (Eq. (6) with the equilibrium
@@ -77,22 +77,18 @@ __device__ __forceinline__ void stp(LBM_GLOBAL char* __restrict__ base, uint32_t
     else *(LBM_GLOBAL S*)(base + off) = Traits<S>::store(v);
 }
 
-// Byte offsets of the population layout split into a part shared by the
+// Byte offsets of the population layout (pop_index: tiles of T nodes with
+// their 27 directions as runs of T values) split into a part shared by the
 // directions and a part shared by the nodes: population a of node n sits at
-// node_off(n) + plane_off(a).  Planes [27][npad] for 2-byte storage; tiles of
-// T nodes with their 27 directions as runs of T values otherwise (pop_index).
-// The direction part is uniform, so the kernels add it to the buffer's base
-// (scalar arithmetic) and keep one per-lane offset for every direction.
+// node_off(n) + dir_off(a).  The direction part is uniform, so the kernels
+// add it to the buffer's base (scalar arithmetic) and keep one per-lane
+// offset for every direction.
 template <class S>
 __device__ __forceinline__ uint32_t node_off(uint32_t n) {
     constexpr uint32_t SZ = sizeof(S);
-    return SZ == 2 ? n * SZ : pop_index(n, 0u, 0u, SZ) * SZ;
+    return pop_index(n, 0u, 0u, SZ) * SZ;
 }
-template <class S>
-__device__ __forceinline__ uint32_t plane_off(int al, uint32_t npad) {
-    constexpr uint32_t SZ = sizeof(S);
-    return SZ == 2 ? (uint32_t)al * npad * SZ : (uint32_t)al * ((1u << pop_tile_shift(SZ)) * SZ);
-}
+__device__ __forceinline__ constexpr uint32_t dir_off(int al) { return (uint32_t)al * POP_RUN_BYTES; }
 
 // Full-expansion equilibrium (product form of Eq. (3)) in FP64, one direction.
 __device__ inline double feq1(int a, double rho, const double u[3]) {
@@ -334,7 +330,6 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
         rp[q] = *(const LBM_GLOBAL RowWord2*)(rt + e * 8u);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const uint32_t npad = (uint32_t)a.npad;
     const uint32_t own = node_off<S>((uint32_t)i);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -347,19 +342,19 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
             const int al = 9 * kz + 3 * ky + kx;
             const int k = 2 - kx;              // bit of the source cell x - cx
             if (al == 13) {
-                f[al] = ldp<S>(fin + plane_off<S>(13, npad), own);
+                f[al] = ldp<S>(fin + dir_off(13), own);
                 continue;
             }
             const bool fl = (win >> k) & 1u;
             const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
-            // pulled value: plane al of the source node; bounce-back: plane
-            // abar of this node.  Both offsets are taken from the lower of the
-            // two planes, so that neither is negative.
+            // pulled value: direction al of the source node; bounce-back:
+            // direction abar of this node.  Both offsets are taken from the
+            // lower of the two directions' runs, so that neither is negative.
             const int lo = al < 13 ? al : 26 - al;
-            const uint32_t gap = plane_off<S>(26 - 2 * lo, npad);     // plane(hi) - plane(lo)
+            const uint32_t gap = dir_off(26 - 2 * lo);     // run(hi) - run(lo)
             const uint32_t pull = node_off<S>((uint32_t)src) + (al > 13 ? gap : 0u);
             const uint32_t bounce = own + (al < 13 ? gap : 0u);
-            f[al] = ldp<S>(fin + plane_off<S>(lo, npad), fl ? pull : bounce);
+            f[al] = ldp<S>(fin + dir_off(lo), fl ? pull : bounce);
             if (WALLS && !fl) wallmask |= 1u << al;
         }
     }
@@ -457,7 +452,7 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
                 cum += (uint32_t)__popcll(B[k]);
                 if (wl) {
                     r[k] = rec[idx];
-                    f2[k] = ldp<S>(fin + plane_off<S>(al, (uint32_t)a.npad), own0);
+                    f2[k] = ldp<S>(fin + dir_off(al), own0);
                 }
             }
         }
@@ -721,7 +716,7 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             mon[8] = qout;
         }
 #pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S, NT>(fout + plane_off<S>(al, (uint32_t)a.npad), node_off<S>((uint32_t)i), f[al]);
+        for (int al = 0; al < 27; ++al) stp<S, NT>(fout + dir_off(al), node_off<S>((uint32_t)i), f[al]);
         // after the stores, so the populations are no longer live
         if (sp != nullptr && sp->linkmask != 0u)
             update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);

@@ -19,21 +19,23 @@ constexpr int MAX_DIM = 1023;
 constexpr int BLOCK = 256;            // threads per work-group of the step kernel
 constexpr int MON_WORDS = 10;         // doubles per work-group monitor partial
 
-// Population layout.  4- and 8-byte populations are stored in tiles of
-// 256-byte runs: T = 256 / size consecutive nodes (64 in FP32, 32 in FP64)
-// form a tile that holds their 27 directions one after another, each as one
-// run of T consecutive values, so element (node i, direction a) is at
+// Population layout: tiles of 256-byte runs.  T = 256 / size consecutive
+// nodes (128 for 2-byte storage, 64 in FP32, 32 in FP64) form a tile that
+// holds their 27 directions one after another, each as one run of T
+// consecutive values, so element (node i, direction a) is at
 // (i / T) 27 T + a T + i % T.  A wave's loads and stores of one direction
 // then cover whole runs, and the 27 runs of a tile are adjacent in memory.
-// 2-byte populations keep one plane per direction, element a npad + i (a
-// 64-node run of them would be a single 128-byte line; planes measured
-// faster for them).  npad is a multiple of 256, so every tile is whole.
+// (With 64-node runs of 2-byte values, single 128-byte lines, one plane per
+// direction measured faster; 256-byte runs measured 3 % faster than planes.)
+// npad is a multiple of 256, so every tile is whole.
 constexpr uint32_t POP_RUN_BYTES = 256;
-__host__ __device__ __forceinline__ constexpr uint32_t pop_tile_shift(uint32_t sz) { return sz == 8 ? 5u : 6u; }
+__host__ __device__ __forceinline__ constexpr uint32_t pop_tile_shift(uint32_t sz) {
+    return sz == 8 ? 5u : (sz == 4 ? 6u : 7u);
+}
 __host__ __device__ __forceinline__ constexpr uint32_t pop_index(uint32_t i, uint32_t a, uint32_t npad, uint32_t sz) {
-    return sz == 2 ? a * npad + i
-                   : (i >> pop_tile_shift(sz)) * (27u << pop_tile_shift(sz)) + (a << pop_tile_shift(sz)) +
-                         (i & ((1u << pop_tile_shift(sz)) - 1u));
+    (void)npad;
+    return (i >> pop_tile_shift(sz)) * (27u << pop_tile_shift(sz)) + (a << pop_tile_shift(sz)) +
+           (i & ((1u << pop_tile_shift(sz)) - 1u));
 }
 
 // Row table entry k of a row: fluid bits of the 32 cells 30k - 1 .. 30k + 30
