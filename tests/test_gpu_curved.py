@@ -149,20 +149,23 @@ def test_aneurysm256_prefix_exact_wall_distances(storage, tol):
     assert eps_u(u, u_ref) < tol
 
 
-def test_batch_with_curved_walls_equals_solo():
+@pytest.mark.parametrize("cfg", [(0, 256, 0, 0, 0), (1, 256, 0, 0, 0), (1, 128, 0, 64, 1)])
+def test_batch_with_curved_walls_equals_solo(cfg):
     """A batch that mixes curved-wall and plain domains steps each of them
-    bit-identically to stepping it alone."""
+    bit-identically to stepping it alone, with per-step launches and with
+    the persistent kernel (the blend runs inside the shared step)."""
     from paper_2101_11107_amd import lbm
     cases = [synth.random_tiny_case(s, nx=31, ny=9, nz=8) for s in (1, 3)] + [synth.aneurysm_case(64, 1)]
     wqs = [_random_q(cases[0], 7), None, (synth.wall_links(cases[2].mask, 0),
                                           synth.wall_distances(cases[2], synth.wall_links(cases[2].mask, 0)))]
     steps = 37
     for storage in ("f64", "f32"):
-        print(f"case curved batch {storage}", flush=True)
+        print(f"case curved batch {storage} cfg {cfg}", flush=True)
         doms = [lbm.Domain(c, storage=storage, wall_q=w) for c, w in zip(cases, wqs)]
         for d in doms:
             d.init()
         b = lbm.Batch(doms)
+        b.set_config(cfg)
         b.step(steps)
         b.status()
         got = [d.populations().cpu().numpy() for d in doms]
