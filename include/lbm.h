@@ -255,13 +255,15 @@ int lbm_monitors(lbm_domain* dom, double out[10]);
  * conversion from the storage type.  Asynchronous. */
 int lbm_read_populations(lbm_domain* dom, double* f_dev);
 
-/* Checkpoint: raw state (populations in storage format, outlet velocities,
- * time).  With host == NULL, *bytes receives the size; otherwise *bytes must
- * be at least that size.  Synchronizes the stream. */
+/* Checkpoint: raw state (populations in storage format and in this build's
+ * device layout, the open-boundary terms, time).  With host == NULL, *bytes
+ * receives the size; otherwise *bytes must be at least that size.
+ * Synchronizes the stream. */
 int lbm_get_state(lbm_domain* dom, void* host, size_t* bytes);
 
-/* Restore a checkpoint taken from a domain with the same mask and storage.
- * EINVAL if the header does not match.  Synchronizes the stream. */
+/* Restore a checkpoint taken from a domain with the same mask, storage and
+ * row-tile edge.  EINVAL if the header does not match (including a state
+ * written in another layout version).  Synchronizes the stream. */
 int lbm_set_state(lbm_domain* dom, const void* host, size_t bytes);
 
 /* Host-side evaluation of the inlet speed U(r, t) used by the velocity inlet

@@ -335,6 +335,7 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->n = nfluid;
         d->npad = (int)npad;
         d->W = (nx + lbm::ROW_SPAN - 1) / lbm::ROW_SPAN;
+        d->row_tile = row_tile;
         d->rows = (ny + 2) * (nz + 2);
         d->nblocks = (int)(npad / lbm::BLOCK);
         d->blocks_per_xcd = (d->nblocks + 7) / 8;
@@ -987,11 +988,16 @@ int lbm_read_populations(lbm_domain* d, double* f_dev) {
 }
 
 namespace {
+// Version 2: populations in tiles of 256-byte runs for every storage form
+// (version 1 kept one plane per direction for the 2-byte forms); the node
+// order's row-tile edge and the population tile are recorded and must match.
+constexpr uint32_t STATE_VERSION = 2;
 struct StateHeader {
     char magic[8];
     uint32_t version, storage;
     int64_t n, nspec, npad, t;   // nspec: number of open-boundary links
     uint64_t pop_bytes;
+    uint32_t row_tile, pop_tile; // row-tile edge of the node order; nodes per population tile
 };
 }  // namespace
 
@@ -1006,8 +1012,10 @@ int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
     StateHeader h{};
     std::memcpy(h.magic, "LBMSTAT1", 8);
-    h.version = 1;
+    h.version = STATE_VERSION;
     h.storage = (uint32_t)d->storage;
+    h.row_tile = (uint32_t)d->row_tile;
+    h.pop_tile = 1u << lbm::pop_tile_shift((uint32_t)storage_bytes(d->storage));
     h.n = d->n;
     h.nspec = (int64_t)d->nlinks();
     h.npad = d->npad;
@@ -1034,7 +1042,10 @@ int lbm_set_state(lbm_domain* d, const void* host, size_t bytes) {
     if (bytes < sizeof h) return fail(LBM_EINVAL, "state too short");
     std::memcpy(&h, host, sizeof h);
     const size_t need = sizeof(StateHeader) + d->pop_bytes + d->nlinks() * sizeof(double);
-    if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0 || h.version != 1 || h.storage != (uint32_t)d->storage ||
+    if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0 || h.version != STATE_VERSION ||
+        h.row_tile != (uint32_t)d->row_tile ||
+        h.pop_tile != (1u << lbm::pop_tile_shift((uint32_t)storage_bytes(d->storage))) ||
+        h.storage != (uint32_t)d->storage ||
         h.n != d->n || h.nspec != (int64_t)d->nlinks() || h.npad != d->npad || h.pop_bytes != d->pop_bytes ||
         h.t < 0 || bytes < need)
         return fail(LBM_EINVAL, "state header does not match this domain");

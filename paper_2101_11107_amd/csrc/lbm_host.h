@@ -44,6 +44,7 @@ struct lbm_domain {
     int W = 0;
     int rows = 0;
     int nblocks = 0, blocks_per_xcd = 0;
+    int row_tile = 0;                      // row-tile edge of the node order
     std::vector<uint32_t> node_words;      // [npad]
     std::vector<lbm::RowEntry> rowtab;     // [rows][W]
     std::vector<lbm::SpecialNode> spec;

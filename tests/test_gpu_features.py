@@ -79,8 +79,17 @@ def test_checkpoint_header_is_validated():
     other = lbm.Domain(case, storage="f16s")
     with pytest.raises(lbm.LbmError):
         other.set_state(a.get_state())
+    # another node order (row-tile edge) or another layout version is refused
+    reordered = lbm.Domain(case, storage="f32", row_tile=4)
+    with pytest.raises(lbm.LbmError):
+        reordered.set_state(a.get_state())
+    old = bytearray(a.get_state())
+    old[8:12] = (1).to_bytes(4, "little")
+    with pytest.raises(lbm.LbmError):
+        a.set_state(bytes(old))
     a.close()
     other.close()
+    reordered.close()
 
 
 def test_mass_balance_every_step_open_system():
