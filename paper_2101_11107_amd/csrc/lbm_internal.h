@@ -1,5 +1,6 @@
-// Internal declarations shared by the host side (lbm_api.cpp) and the HIP
-// kernels (lbm_kernels.hip) of the library.  Not part of the public ABI.
+// Internal declarations shared by the host side (lbm_api.cpp,
+// lbm_batch_api.cpp) and the HIP kernels (lbm_step.hip, lbm_batch.hip,
+// lbm_kernels.hip) of the library.  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -155,7 +156,8 @@ struct BatchConfig {
     int group_mb;        // domains stepped together per group, by population working set (0 = all)
 };
 
-// Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
+// Launchers (lbm_kernels.hip; launch_step dispatches to the per-storage step
+// launchers of lbm_step.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_t stream);
 // The step launcher of one storage type (lbm_step.hip, one translation unit each).
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 0>);

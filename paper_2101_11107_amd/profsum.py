@@ -18,6 +18,7 @@ import argparse
 import csv
 import glob
 import hashlib
+import re
 import json
 import os
 
@@ -27,13 +28,21 @@ STEP = "k_step"           # demangled (k_step<...>) or mangled (...k_stepI...) n
 COPY = "__amd_rocclr_copyBuffer"
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed, so
+    that editing a comment does not change the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the step kernel's sources (the bench accepts a summary only
-    when it matches)."""
+    """Hash of the step kernel's code (comments and layout ignored); the
+    bench accepts a summary only when it matches."""
     h = hashlib.sha256()
     for name in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2101_11107_amd", "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
