@@ -166,7 +166,9 @@ def test_nonfinite_state_reported_unstable():
     dom.init()
     dom.step(2)
     blob = bytearray(dom.get_state())
-    hdr = 8 + 4 + 4 + 8 * 4 + 8            # header of the state blob
+    # header of the state blob: magic, version, storage, n, nspec, npad, t,
+    # population bytes, row-tile edge, population tile
+    hdr = 8 + 4 + 4 + 8 * 4 + 8 + 4 + 4
     blob[hdr: hdr + 4] = struct.pack("<f", float("nan"))
     dom.set_state(bytes(blob))
     dom.step(2)
