@@ -64,8 +64,8 @@ def read_traffic(storage, workload):
         return None
 
 
-def run_form(torch, lbm, case, storage, warmup, steps, want_u=False, wall_q=None):
-    dom = lbm.Domain(case, storage=storage, device="cuda:0", wall_q=wall_q)
+def run_form(torch, lbm, case, storage, warmup, steps, want_u=False, wall_q=None, streaming="auto"):
+    dom = lbm.Domain(case, storage=storage, device="cuda:0", wall_q=wall_q, streaming=streaming)
     dom.init()
     dom.step(warmup)
     dom.stream.synchronize()
@@ -80,7 +80,7 @@ def run_form(torch, lbm, case, storage, warmup, steps, want_u=False, wall_q=None
     ms = ev0.elapsed_time(ev1)
     mon = dom.monitors()
     out = dict(n=dom.n, ms=ms, ms_per_step=ms / steps, mlups=dom.n * steps / (ms * 1e-3) / 1e6,
-               monitors=mon)
+               monitors=mon, streaming="inplace" if dom.in_place() else "pull")
     if want_u:
         _, u = dom.moments()
         out["u"] = u.cpu().numpy()
@@ -314,6 +314,8 @@ def main():
     ap.add_argument("--walls", default="halfway", choices=["halfway", "curved"],
                     help="wall rule of the timed run: halfway bounce-back, or interpolated bounce-back with the "
                          "exact wall distance on every wall link (Eq. (9)-(10))")
+    ap.add_argument("--streaming", default="auto", choices=["auto", "pull", "inplace"],
+                    help="streaming pattern of the timed run (lbm_set_streaming; auto picks by size)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other storage forms and sizes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector protocol")
@@ -350,8 +352,9 @@ def main():
         wall_q, nlinks = (links, synth.wall_distances(case, links)), int(len(links))
         workload += "_curved"
     main_run = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=not args.no_extra,
-                        wall_q=wall_q)
-    note(f"{workload} {args.storage}: {main_run['mlups']:.1f} MLUPS, {main_run['ms_per_step'] * 1e3:.2f} us per step")
+                        wall_q=wall_q, streaming=args.streaming)
+    note(f"{workload} {args.storage} ({main_run['streaming']} streaming): {main_run['mlups']:.1f} MLUPS, "
+         f"{main_run['ms_per_step'] * 1e3:.2f} us per step")
     traffic = read_traffic(args.storage, workload)
     line = {
         "metric": "fluid-node MLUPS (D3Q27 CHM-MRT fused stream-collide step)",
@@ -368,7 +371,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}_seed0_womersley_alpha3_period{case.period}", "box": [size] * 3,
                    "fluid_nodes": main_run["n"], "storage": args.storage, "tau": round(case.tau, 6),
-                   "steps_per_graph": 16, "walls": args.walls},
+                   "steps_per_graph": 16, "walls": args.walls, "streaming": main_run["streaming"]},
         "roofline": roofline(main_run["n"], main_run["ms_per_step"], args.storage, traffic, nlinks),
     }
     if nlinks:
@@ -383,6 +386,17 @@ def main():
 
     if not args.no_extra:
         also = []
+        # the same run with the other streaming pattern (same values, other
+        # places between steps)
+        other = "pull" if main_run["streaming"] == "inplace" else "inplace"
+        alt = run_form(torch, lbm, case, args.storage, args.warmup, args.steps, want_u=True, streaming=other)
+        also.append({"workload": workload, "storage": args.storage, "streaming": other,
+                     "mlups": round(alt["mlups"], 1),
+                     "roofline_frac": roofline(alt["n"], alt["ms_per_step"], args.storage, None)["frac"],
+                     "rate_vs_value": round(alt["mlups"] / main_run["mlups"], 3),
+                     "velocity_bitwise_equal": bool(np.array_equal(alt["u"], main_run["u"]))})
+        note(f"{other} streaming: {alt['mlups']:.1f} MLUPS")
+        pull_run = alt if other == "pull" else main_run
         # every storage form at both geometries, velocity error and mass drift
         # against the FP64 run of the same geometry after the same steps
         for wl in (workload, "aneurysm256" if workload == "aneurysm512" else "aneurysm512"):
@@ -421,7 +435,8 @@ def main():
                      "vs_f64": {st: {k: (round(v, 10) if isinstance(v, float) else v) for k, v in ps[st].items()}
                                 for st in ("f32", "f16s", "bf16s")}})
         note(f"precision study 40000 steps: {also[-1]['vs_f64']}")
-        also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, main_run))
+        # curved walls stream with pull: compared with the halfway pull run
+        also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, pull_run))
         note(f"curved walls: {also[-1]['mlups']:.1f} MLUPS, pipe order {also[-1]['pipe_order']}")
         # SRT comparator: its step rate on the same run, and the stability sweep
         r = run_form(torch, lbm, dataclasses.replace(case, collision="srt2"), args.storage, args.warmup,

@@ -171,6 +171,41 @@ int lbm_set_params(lbm_domain* dom, const lbm_params* p);
 enum { LBM_COLLISION_CHM_MRT = 0, LBM_COLLISION_SRT2 = 1 };
 int lbm_set_collision(lbm_domain* dom, int kind);
 
+/* Streaming pattern of lbm_step.  The step is the pull scheme of Sec. 2.1
+ * (stream f_a(x, t+1) = f*_a(x - c_a, t), halfway bounce-back and the
+ * open-boundary rules on the links whose source is not fluid) followed by the
+ * collision; the pattern only decides where the populations are kept between
+ * steps, never their values.
+ * LBM_STREAM_PULL: two population buffers, each step reads one and writes the
+ * other.
+ * LBM_STREAM_INPLACE: one buffer, steps alternating between two kinds.  The
+ * first reads f*_a(x - c_a, t) from slot abar of the source node (or the
+ * node's own f*_abar from its slot a on a wall or open link) and writes
+ * f*_abar(x, t+1) back to that same place; the next reads slot a of x and
+ * writes f*_a(x, t+2) to slot abar of x.  Every place is read and written by
+ * one node, so the buffer is updated in place; results are bitwise equal to
+ * LBM_STREAM_PULL.  One buffer of populations fits the 256 MB Infinity Cache
+ * where two may not, and every other step touches only its own node.
+ * Readers of the state (lbm_moments, lbm_average, lbm_read_populations,
+ * lbm_get_state) and batches first move the populations back to the pull
+ * layout (one extra pass, on the domain's stream); the next in-place step
+ * moves them again.  Memory use is unchanged.  May be called at any time.
+ * EINVAL for an unknown mode, or LBM_STREAM_INPLACE on a domain with curved
+ * walls (lbm_create_domain_curved).
+ * LBM_STREAM_AUTO (the default): in place where one population buffer is at
+ * most 224 MiB and the two of the pull scheme are more (one buffer stays in
+ * the 256 MB Infinity Cache, two do not), pull otherwise.  Measured at the
+ * 512^3 aneurysm: FP32 (229 MB per buffer) steps 1.2-1.3 times faster in
+ * place; the 2-byte forms (two buffers of 115 MB fit) and FP64 (one buffer
+ * of 458 MB does not) step faster with pull.  Never in place with curved
+ * walls. */
+enum { LBM_STREAM_PULL = 0, LBM_STREAM_INPLACE = 1, LBM_STREAM_AUTO = 2 };
+int lbm_set_streaming(lbm_domain* dom, int mode);
+
+/* *in_place = 1 when lbm_step streams in place (the mode of
+ * lbm_set_streaming resolved for this domain), else 0.  EINVAL for NULL. */
+int lbm_streaming_in_place(const lbm_domain* dom, int* in_place);
+
 /* Velocity inlet on the INLET ghost cells: the wall velocity of a link is
  * u_w = axis * U(r, t) at the link midpoint, where r is the distance from the
  * line through `center` along `axis` and U is the Womersley profile

@@ -100,8 +100,11 @@ namespace lbm_host {
 lbm::StepArgs make_args(const lbm_domain* d) {
     lbm::StepArgs a{};
     char* base = d->dev;
-    a.fin = base + (d->cur == 0 ? d->off_popA : d->off_popB);
-    a.fout = base + (d->cur == 0 ? d->off_popB : d->off_popA);
+    const bool in_a = (d->cur ^ d->pop_flip) == 0;
+    char* in = base + (in_a ? d->off_popA : d->off_popB);
+    a.fin = in;
+    // in-place streaming reads and writes one buffer
+    a.fout = d->layout != LAYOUT_PULL ? in : base + (in_a ? d->off_popB : d->off_popA);
     a.node = (const uint32_t*)(base + d->off_node);
     a.rowtab = (const lbm::RowEntry*)(base + d->off_rowtab);
     a.spec = (const SpecialNode*)(base + d->off_spec);
@@ -242,29 +245,74 @@ int prepare_links(lbm_domain* d) {
 
 }  // namespace lbm_host
 
+bool lbm_domain::use_inplace() const {
+    if (!crec.empty() || stream_mode == LBM_STREAM_PULL) return false;
+    if (stream_mode == LBM_STREAM_INPLACE) return true;
+    // one buffer fits the Infinity Cache, the two of the pull scheme do not
+    return pop_bytes <= lbm_host::INPLACE_MAX_BYTES && 2 * pop_bytes > lbm_host::INPLACE_MAX_BYTES;
+}
+
+namespace lbm_host {
+
+int sync_pull(lbm_domain* d) {
+    if (d->layout == LAYOUT_PULL) return LBM_OK;
+    lbm::StepArgs a = make_args(d);
+    if (d->layout == LAYOUT_REVERSED) {
+        // slot reversal in place
+        HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, d->stream), "in-place layout");
+    } else {
+        // the streamed layout is a permutation of the post-collision values:
+        // gathered into the other buffer, which becomes the one read next
+        const bool in_a = (d->cur ^ d->pop_flip) == 0;
+        a.fout = d->dev + (in_a ? d->off_popB : d->off_popA);
+        HIP_TRY(lbm::launch_inplace_unstream(d->storage, a, d->stream), "in-place layout");
+        d->pop_flip ^= 1;
+    }
+    d->layout = LAYOUT_PULL;
+    return LBM_OK;
+}
+
+}  // namespace lbm_host
+
 namespace {
 
 // Launch nsteps steps; the last one accumulates the monitors.
+// The bookkeeping of one step: the next time slot; an in-place step stays on
+// its buffer and turns the layout (reversed <-> streamed).
+void advance_state(lbm_domain* d) {
+    d->cur ^= 1;
+    if (d->layout != LAYOUT_PULL) {
+        d->pop_flip ^= 1;
+        d->layout = LAYOUT_REVERSED + LAYOUT_STREAMED - d->layout;
+    }
+}
+
 int launch_steps_eager(lbm_domain* d, int nsteps) {
     const bool big = 2 * d->pop_bytes > lbm_host::STREAM_STORE_BYTES;
     for (int k = 0; k < nsteps; ++k) {
         lbm::StepArgs a = make_args(d);
-        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(), big, d->collision == 1,
-                                 !d->crec.empty()};
+        const int ip = d->layout == LAYOUT_REVERSED   ? lbm::STREAM_NEIGHBOUR
+                       : d->layout == LAYOUT_STREAMED ? lbm::STREAM_LOCAL
+                                                      : lbm::STREAM_PULL;
+        const lbm::StepVariant v{k == nsteps - 1, d->rates_one(), d->periodic_yz(), big && ip == lbm::STREAM_PULL,
+                                 d->collision == 1, !d->crec.empty(), ip};
         HIP_TRY(lbm::launch_step(d->storage, a, v, d->stream), "step kernel");
-        d->cur ^= 1;
+        advance_state(d);
     }
     return LBM_OK;
 }
 
-// Capture GRAPH_STEPS steps starting from the current parity into a graph.
+// Capture GRAPH_STEPS steps starting from the current state into a graph.
 int build_graph(lbm_domain* d) {
-    const int par = d->cur;
+    const int cur = d->cur, flip = d->pop_flip, layout = d->layout, key = d->graph_key();
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(d->stream, hipStreamCaptureModeRelaxed), "graph capture begin");
     int rc = launch_steps_eager(d, GRAPH_STEPS);
     hipError_t e = hipStreamEndCapture(d->stream, &g);
-    d->cur = par;   // nothing ran during capture
+    // nothing ran during capture
+    d->cur = cur;
+    d->pop_flip = flip;
+    d->layout = layout;
     if (rc) {
         if (g) hipGraphDestroy(g);
         return rc;
@@ -274,7 +322,15 @@ int build_graph(lbm_domain* d) {
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-    d->graph[par] = ex;
+    d->graph[key] = ex;
+    return LBM_OK;
+}
+
+// Pull layout -> reversed layout, in place (the first in-place step reads it).
+int enter_inplace(lbm_domain* d) {
+    const lbm::StepArgs a = make_args(d);
+    HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, d->stream), "in-place layout");
+    d->layout = LAYOUT_REVERSED;
     return LBM_OK;
 }
 
@@ -805,6 +861,24 @@ int lbm_set_collision(lbm_domain* d, int kind) {
     return LBM_OK;
 }
 
+int lbm_set_streaming(lbm_domain* d, int mode) {
+    if (!d) return fail(LBM_EINVAL, "NULL argument");
+    if (mode != LBM_STREAM_PULL && mode != LBM_STREAM_INPLACE && mode != LBM_STREAM_AUTO)
+        return fail(LBM_EINVAL, "unknown streaming mode");
+    if (mode == LBM_STREAM_INPLACE && !d->crec.empty())
+        return fail(LBM_EINVAL, "in-place streaming does not take curved walls");
+    d->stream_mode = mode;
+    // leaving in-place streaming: the pull step reads the pull layout
+    if (!d->use_inplace() && d->dev) return sync_pull(d);
+    return LBM_OK;
+}
+
+int lbm_streaming_in_place(const lbm_domain* d, int* in_place) {
+    if (!d || !in_place) return fail(LBM_EINVAL, "NULL argument");
+    *in_place = d->use_inplace() ? 1 : 0;
+    return LBM_OK;
+}
+
 int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (!d->dev) return fail(LBM_ESTATE, "no device memory attached");
@@ -814,6 +888,8 @@ int lbm_init_equilibrium(lbm_domain* d, const double* rho, const double* u) {
     if (rc) return rc;
     rc = upload_phase(d, 0);
     if (rc) return rc;
+    d->pop_flip = 0;
+    d->layout = LAYOUT_PULL;
     d->cur = 1;   // the init kernel writes into the "next" buffer of slot 1, i.e. buffer A
     lbm::StepArgs a = make_args(d);
     a.tin = 0;
@@ -840,25 +916,32 @@ int lbm_step(lbm_domain* d, int nsteps) {
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
     int rc = prepare_links(d);
     if (rc) return rc;
+    if (nsteps > 0 && d->use_inplace() && d->layout == LAYOUT_PULL) {
+        rc = enter_inplace(d);
+        if (rc) return rc;
+    }
     int left = nsteps;
     // Long runs replay captured graphs of GRAPH_STEPS launches (no host launch
     // gaps); the default (NULL) stream cannot be captured and runs eagerly.
-    // The graphs of both buffer parities are captured together, on the first
-    // call after a change that dropped them, so a later call (a timed run)
-    // never waits for a capture, whatever parity it starts at.
+    // The graphs of the current state and of the state one step later are
+    // captured together, on the first call after a change that dropped them,
+    // so a later call (a timed run) never waits for a capture, whatever step
+    // parity it starts at.  GRAPH_STEPS is even: a replay ends in the state it
+    // started from.
     if (d->stream != nullptr) {
-        if (nsteps > 0 && (!d->graph[0] || !d->graph[1])) {
-            const int cur = d->cur;
-            for (int par = 0; par < 2 && rc == 0; ++par) {
-                if (d->graph[par]) continue;
-                d->cur = par;
-                rc = build_graph(d);
+        if (nsteps > 0) {
+            const int cur = d->cur, flip = d->pop_flip, layout = d->layout;
+            for (int k = 0; k < 2 && rc == 0; ++k) {
+                if (k == 1) advance_state(d);
+                if (!d->graph[d->graph_key()]) rc = build_graph(d);
             }
             d->cur = cur;
+            d->pop_flip = flip;
+            d->layout = layout;
             if (rc) return rc;
         }
         while (left >= GRAPH_STEPS) {
-            HIP_TRY(hipGraphLaunch(d->graph[d->cur], d->stream), "graph launch");
+            HIP_TRY(hipGraphLaunch(d->graph[d->graph_key()], d->stream), "graph launch");
             left -= GRAPH_STEPS;
         }
     }
@@ -883,6 +966,8 @@ int lbm_moments(lbm_domain* d, double* rho, double* u) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
     if (!rho && !u) return LBM_OK;
+    int rc = sync_pull(d);
+    if (rc) return rc;
     lbm::StepArgs a = make_args(d);
     HIP_TRY(lbm::launch_moments(d->storage, a, rho, u, nullptr, 0, 0.0, d->stream), "moments kernel");
     return LBM_OK;
@@ -947,11 +1032,15 @@ int lbm_average(lbm_domain* d, int op, double* u_avg) {
                 d->drop_graphs();
             }
             return LBM_OK;
-        case LBM_AVG_ACCUMULATE:
+        case LBM_AVG_ACCUMULATE: {
             if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+            const int rc = sync_pull(d);
+            if (rc) return rc;
+            a = make_args(d);
             HIP_TRY(lbm::launch_moments(d->storage, a, nullptr, nullptr, acc, 1, 0.0, d->stream), "average accumulate");
             d->avg_count += 1;
             return LBM_OK;
+        }
         case LBM_AVG_READ:
             if (!u_avg) return fail(LBM_EINVAL, "u_avg is NULL");
             if (d->avg_count == 0) return fail(LBM_ESTATE, "nothing accumulated");
@@ -982,6 +1071,8 @@ int lbm_monitors(lbm_domain* d, double out[10]) {
 int lbm_read_populations(lbm_domain* d, double* f_dev) {
     if (!d || !f_dev) return fail(LBM_EINVAL, "NULL argument");
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    const int rc = sync_pull(d);
+    if (rc) return rc;
     lbm::StepArgs a = make_args(d);
     HIP_TRY(lbm::launch_read_populations(d->storage, a, f_dev, d->stream), "population read");
     return LBM_OK;
@@ -1010,6 +1101,9 @@ int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     }
     if (*bytes < need) return fail(LBM_EINVAL, "state buffer too small");
     if (!d->initialized) return fail(LBM_ESTATE, "call lbm_init_equilibrium first");
+    // the state is kept in the pull layout
+    const int rc = sync_pull(d);
+    if (rc) return rc;
     StateHeader h{};
     std::memcpy(h.magic, "LBMSTAT1", 8);
     h.version = STATE_VERSION;
@@ -1023,7 +1117,7 @@ int lbm_get_state(lbm_domain* d, void* host, size_t* bytes) {
     h.pop_bytes = d->pop_bytes;
     char* p = (char*)host;
     std::memcpy(p, &h, sizeof h);
-    const size_t cur_off = d->cur == 0 ? d->off_popA : d->off_popB;
+    const size_t cur_off = (d->cur ^ d->pop_flip) == 0 ? d->off_popA : d->off_popB;
     HIP_TRY(hipMemcpyAsync(p + sizeof h, d->dev + cur_off, d->pop_bytes, hipMemcpyDeviceToHost, d->stream),
             "state copy");
     if (d->nlinks())
@@ -1053,6 +1147,8 @@ int lbm_set_state(lbm_domain* d, const void* host, size_t bytes) {
     if (rc) return rc;
     const char* p = (const char*)host;
     d->cur = 0;
+    d->pop_flip = 0;
+    d->layout = LAYOUT_PULL;
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_popA, p + sizeof h, d->pop_bytes, hipMemcpyHostToDevice, d->stream),
             "state upload");
     if (d->nlinks())

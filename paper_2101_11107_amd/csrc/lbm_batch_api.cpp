@@ -78,7 +78,10 @@ int refresh_tables(lbm_batch* b) {
     for (size_t k = 0; !stale && k < b->doms.size(); ++k) stale = b->built_parity[k] != b->doms[k]->cur;
     for (lbm_domain* d : b->doms) {
         if (d->links_dirty) stale = true;
-        int rc = prepare_links(d);
+        // the batch kernels step the pull layout
+        int rc = sync_pull(d);
+        if (rc) return rc;
+        rc = prepare_links(d);
         if (rc) return rc;
         // the domain's own stream may hold its uploads; the batch runs on its own stream
         HIP_TRY(hipStreamSynchronize(d->stream), "domain stream synchronize");

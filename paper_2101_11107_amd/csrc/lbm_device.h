@@ -27,6 +27,8 @@
 
 #include "lbm_internal.h"
 
+#include <type_traits>
+
 namespace lbm {
 namespace {
 
@@ -295,10 +297,16 @@ typedef uint32_t RowWord2 __attribute__((ext_vector_type(2)));
 // The nine row-table entries are loaded first and the population loads issued
 // after all of them (vector loads retire in order, so interleaving them would
 // serialize the rows).
-template <class S, bool PER, bool WALLS>
+// MODE STREAM_PULL: the pull layout.  MODE STREAM_NEIGHBOUR: the reversed
+// layout of in-place streaming: direction al comes from slot abar of the
+// source node, or from slot al of this node on a wall link; loc[al] keeps
+// that byte offset (from fin), where f*_abar of this node is written back.
+// MODE GATHER_WALL_BITS: no population loads, only the wall links.
+constexpr int GATHER_WALL_BITS = 3;
+template <class S, bool PER, bool WALLS, int MODE = STREAM_PULL>
 __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a, int i,
                                             uint32_t w, typename Traits<S>::T (&f)[27],
-                                            uint32_t& wallmask) {
+                                            uint32_t& wallmask, uint32_t (&loc)[27]) {
     constexpr uint32_t SZ = sizeof(S);
     const LBM_GLOBAL char* rt = (const LBM_GLOBAL char*)a.rowtab;
     const int x = (int)(w & 1023u);
@@ -342,11 +350,22 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
             const int al = 9 * kz + 3 * ky + kx;
             const int k = 2 - kx;              // bit of the source cell x - cx
             if (al == 13) {
-                f[al] = ldp<S>(fin + dir_off(13), own);
+                if (MODE == STREAM_NEIGHBOUR) loc[13] = own + dir_off(13);
+                if (MODE != GATHER_WALL_BITS) f[al] = ldp<S>(fin + dir_off(13), own);
                 continue;
             }
             const bool fl = (win >> k) & 1u;
+            if (MODE == GATHER_WALL_BITS) {
+                if (!fl) wallmask |= 1u << al;
+                continue;
+            }
             const int src = (k == 0) ? base - 1 : (k == 1 ? base : base + (int)((win >> 1) & 1u));
+            if (MODE == STREAM_NEIGHBOUR) {
+                loc[al] = fl ? node_off<S>((uint32_t)src) + dir_off(26 - al) : own + dir_off(al);
+                f[al] = ldp<S>(fin, loc[al]);
+                if (WALLS && !fl) wallmask |= 1u << al;
+                continue;
+            }
             // pulled value: direction al of the source node; bounce-back:
             // direction abar of this node.  Both offsets are taken from the
             // lower of the two directions' runs, so that neither is negative.
@@ -366,15 +385,36 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
 // f_a = -f*_abar + add (evaluated in FP64, rounded once).  wall_force: add the
 // halfway wall force of the wall links to F (the curved-wall blend adds it
 // otherwise).
-template <class S, bool MON>
+// In-place streaming (IP = STREAM_NEIGHBOUR, STREAM_LOCAL) reads the same
+// values from the places the layout gives them (see STREAM_PULL); own is
+// node_off of this node, and loc receives the neighbour step's offsets.
+template <class S>
+__device__ __forceinline__ uint32_t inplace_special_off(const LBM_GLOBAL SpecialNode* __restrict__ sp, int al,
+                                                        uint32_t nonfluid, uint32_t own) {
+    // a fluid source (also across a periodic x edge): slot abar instead of
+    // slot al of that node; a wall or open link: slot al of this node
+    return ((nonfluid >> al) & 1u) ? own + dir_off(al) : sp->off[al] - dir_off(al) + dir_off(26 - al);
+}
+
+template <class S, bool MON, int IP = STREAM_PULL>
 __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a,
                                                const LBM_GLOBAL SpecialNode* __restrict__ sp,
                                                typename Traits<S>::T (&f)[27], double (&F)[3],
-                                               double& qin, double& qout, bool wall_force) {
+                                               double& qin, double& qout, bool wall_force,
+                                               uint32_t (&loc)[27], uint32_t own) {
     using T = typename Traits<S>::T;
-#pragma unroll
-    for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin, sp->off[al]);
     const uint32_t wm = sp->wallmask, lm = sp->linkmask;
+#pragma unroll
+    for (int al = 0; al < 27; ++al) {
+        if (IP == STREAM_PULL) {
+            f[al] = ldp<S>(fin, sp->off[al]);
+        } else if (IP == STREAM_NEIGHBOUR) {
+            loc[al] = inplace_special_off<S>(sp, al, wm | lm, own);
+            f[al] = ldp<S>(fin, loc[al]);
+        } else {
+            f[al] = ldp<S>(fin, own + dir_off(al));
+        }
+    }
     if (MON && wall_force && wm) {
 #pragma unroll
         for (int al = 0; al < 27; ++al) {
@@ -633,14 +673,21 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
 // Logical block lb of the domain (BS consecutive nodes).  Used by the
 // single-domain kernel and by the batched kernels, so a node's arithmetic is
 // the same in both.  CURVED: blend the curved-wall links of ordinary nodes
-// (a domain without weight records skips it).
-template <class S, bool MON, int FORM, bool PER, bool NT, int BS, bool CURVED>
+// (a domain without weight records skips it).  IP: the streaming pattern
+// (STREAM_PULL between fin and fout; the in-place steps with fin == fout read
+// and write the places described at STREAM_PULL, with the same values and
+// arithmetic as the pull step).
+template <class S, bool MON, int FORM, bool PER, bool NT, int BS, bool CURVED, int IP = STREAM_PULL>
 __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
+    static_assert(IP == STREAM_PULL || !CURVED, "in-place streaming has no curved walls");
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
     const int i = lb * BS + threadIdx.x;
-    const LBM_GLOBAL char* __restrict__ fin = (const LBM_GLOBAL char*)a.fin;
-    LBM_GLOBAL char* __restrict__ fout = (LBM_GLOBAL char*)a.fout;
+    // the two buffers are distinct only for the pull step
+    using InPtr = std::conditional_t<IP == STREAM_PULL, const LBM_GLOBAL char* __restrict__, const LBM_GLOBAL char*>;
+    using OutPtr = std::conditional_t<IP == STREAM_PULL, LBM_GLOBAL char* __restrict__, LBM_GLOBAL char*>;
+    const InPtr fin = (const LBM_GLOBAL char*)a.fin;
+    const OutPtr fout = (LBM_GLOBAL char*)a.fout;
     double mon[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < a.n) {
         T f[27];
@@ -649,15 +696,24 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
         const LBM_GLOBAL SpecialNode* sp = nullptr;
         const bool curved = CURVED && a.crec != nullptr;
-        // the node's own population offset without its direction part (curved walls)
-        const uint32_t own0 = CURVED ? node_off<S>((uint32_t)i) : 0u;
+        // the node's own population offset without its direction part (curved
+        // walls, in-place streaming)
+        const uint32_t own0 = (CURVED || IP != STREAM_PULL) ? node_off<S>((uint32_t)i) : 0u;
+        // in-place neighbour step: where each direction was read
+        uint32_t loc[27];
         if (!(w & SPECIAL_BIT)) {
-            gather_fast<S, PER, MON || CURVED>(fin, a, i, w, f, wallmask);
+            if (IP == STREAM_LOCAL) {
+#pragma unroll
+                for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin + dir_off(al), own0);
+                if (MON) gather_fast<S, PER, true, GATHER_WALL_BITS>(fin, a, i, w, f, wallmask, loc);
+            } else {
+                gather_fast<S, PER, MON || CURVED, IP>(fin, a, i, w, f, wallmask, loc);
+            }
         } else {
             sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
             // read before the gather's loads, so that using it waits for none of them
             if (curved) wallmask = sp->wallmask;
-            gather_special<S, MON>(fin, a, sp, f, F, qin, qout, !curved);
+            gather_special<S, MON, IP>(fin, a, sp, f, F, qin, qout, !curved, loc, own0);
         }
         if (curved) {
             // every wall link has a record (r = 1: halfway)
@@ -715,8 +771,18 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             mon[7] = qin;
             mon[8] = qout;
         }
+        if (IP == STREAM_PULL) {
 #pragma unroll
-        for (int al = 0; al < 27; ++al) stp<S, NT>(fout + dir_off(al), node_off<S>((uint32_t)i), f[al]);
+            for (int al = 0; al < 27; ++al) stp<S, NT>(fout + dir_off(al), node_off<S>((uint32_t)i), f[al]);
+        } else if (IP == STREAM_NEIGHBOUR) {
+            // f*_abar goes where direction al was read: the source node's slot
+            // abar (the value it pulls next), or this node's slot al
+#pragma unroll
+            for (int al = 0; al < 27; ++al) stp<S, NT>(fout, loc[al], f[26 - al]);
+        } else {
+#pragma unroll
+            for (int al = 0; al < 27; ++al) stp<S, NT>(fout + dir_off(26 - al), own0, f[al]);
+        }
         // after the stores, so the populations are no longer live
         if (sp != nullptr && sp->linkmask != 0u)
             update_links(a, sp, (double)ux, (double)uy, (double)uz, a.tcount[a.tin] + 1);

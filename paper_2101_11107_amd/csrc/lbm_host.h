@@ -22,6 +22,10 @@ constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffe
 // Population working sets above this size do not stay in the 256 MB Infinity
 // Cache; there streaming (non-temporal) stores are faster.
 constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
+// LBM_STREAM_AUTO streams in place where one population buffer is at most
+// this size and the two of the pull scheme are more: one buffer then stays in
+// the 256 MB Infinity Cache, two do not.
+constexpr size_t INPLACE_MAX_BYTES = (size_t)224 << 20;
 
 }  // namespace lbm_host
 
@@ -30,6 +34,10 @@ constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
         hipError_t _e = (expr);                                        \
         if (_e != hipSuccess) return lbm_host::hip_fail(_e, what);     \
     } while (0)
+
+// Layout of an in-place domain's population buffer (lbm::STREAM_PULL has the
+// description of the reversed and streamed layouts).
+enum : int { LAYOUT_PULL = 0, LAYOUT_REVERSED = 1, LAYOUT_STREAMED = 2 };
 
 // A domain: host tables, parameters, the layout of its device memory and its
 // time/buffer bookkeeping.
@@ -77,7 +85,14 @@ struct lbm_domain {
            off_probe = 0, off_crec = 0, off_cbase = 0;
     size_t pop_bytes = 0;
 
+    // cur: time-counter slot of the next step, toggled by every step.  The
+    // population buffer read next is A when cur ^ pop_flip == 0, else B: a
+    // pull step moves to the other buffer with cur; an in-place step stays by
+    // toggling pop_flip with it.
     int cur = 0;
+    int pop_flip = 0;
+    int stream_mode = LBM_STREAM_AUTO;   // lbm_set_streaming
+    int layout = 0;           // the buffer's layout: LAYOUT_PULL, LAYOUT_REVERSED or LAYOUT_STREAMED
     int64_t t = 0;
     int64_t t_upload[2] = {0, 0};
     double trig_host[4] = {1, 0, 1, 0};   // (cos, sin)(omega t) for slots t & 1
@@ -92,9 +107,12 @@ struct lbm_domain {
     int64_t probe_t0 = 0, probe_cap = 0;
     double mon_host[lbm::MON_WORDS] = {0};
 
-    // Captured graphs of GRAPH_STEPS consecutive steps, one per starting buffer
-    // parity.  Kernel arguments are baked in, so any parameter change drops them.
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // Captured graphs of GRAPH_STEPS consecutive steps, one per starting state
+    // (graph_key: time slot, buffer choice, layout).  Kernel arguments are baked
+    // in, so any parameter change drops them.
+    static constexpr int NGRAPH = 12;
+    hipGraphExec_t graph[NGRAPH] = {};
+    int graph_key() const { return cur | (pop_flip << 1) | (layout << 2); }
 
     void drop_graphs() {
         for (auto& g : graph) {
@@ -123,6 +141,8 @@ struct lbm_domain {
         return collision == 0 && s[0] == 1.0 && s[1] == 1.0 && s[2] == 1.0 && s[3] == 1.0;
     }
     bool periodic_yz() const { return (periodic & 6u) != 0; }
+    // whether lbm_step streams in place (LBM_STREAM_AUTO: see lbm.h)
+    bool use_inplace() const;
 };
 
 namespace lbm_host {
@@ -131,5 +151,8 @@ namespace lbm_host {
 lbm::StepArgs make_args(const lbm_domain* d);
 // Upload the open-boundary coefficients and inlet phase if they changed.
 int prepare_links(lbm_domain* d);
+// Bring an in-place domain's populations back to the pull layout (the layout
+// every reader of the state and the batch use); a no-op for the pull layout.
+int sync_pull(lbm_domain* d);
 
 }  // namespace lbm_host

@@ -129,7 +129,21 @@ struct StepVariant {
     bool stream_store;   // non-temporal population stores (working set beyond the Infinity Cache)
     bool srt2;           // the SRT comparator instead of CHM-MRT
     bool curved;         // curved-wall weights (crec set)
+    int inplace;         // 0: pull between two buffers; in-place streaming (fin == fout): 1 the
+                         // neighbour step, 2 the node-local step (STREAM_* below)
 };
+
+// In-place (AA-pattern) streaming keeps one population buffer.  Its layouts:
+//  * reversed (R): the post-collision f*_a(x) of the last step in slot abar of
+//    node x, i.e. the pull layout with every node's slots reversed;
+//  * streamed (S): slot a of node x holds the value that arrives there,
+//    f*_a(x - c_a) from a fluid neighbour, or the node's own f*_abar(x) where
+//    x - c_a is not fluid (bounce-back and open links, before their rules).
+// The neighbour step reads R (direction a of x at (x - c_a, abar), or at
+// (x, a) on a wall or open link) and writes f*_abar of x to that same place,
+// leaving S; the node-local step reads slot a of x and writes f*_a to slot
+// abar, leaving R.  Each location is read and written by one thread only.
+enum : int { STREAM_PULL = 0, STREAM_NEIGHBOUR = 1, STREAM_LOCAL = 2 };
 
 // Several domains stepped by one launch.  Work item k of the launch is block
 // (item_map[k] & ITEM_BLOCK_MASK) of domain (item_map[k] >> ITEM_DOMAIN_SHIFT);
@@ -164,11 +178,24 @@ hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, s
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 1>);
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 2>);
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 3>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 0>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 1>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 2>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 3>);
+hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 0>);
+hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 1>);
+hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 2>);
+hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 3>);
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream);
 hipError_t launch_moments(int storage, const StepArgs& a, double* rho, double* u, double* avg,
                           int avg_mode, double avg_count, hipStream_t stream);
 hipError_t launch_read_populations(int storage, const StepArgs& a, double* out, hipStream_t stream);
+// In-place streaming layouts to and from the pull layout (lbm_step.hip):
+// reverse swaps every node's slots a and abar of a.fin in place (pull <-> R);
+// unstream writes the pull layout of the S state in a.fin into a.fout.
+hipError_t launch_inplace_reverse(int storage, const StepArgs& a, hipStream_t stream);
+hipError_t launch_inplace_unstream(int storage, const StepArgs& a, hipStream_t stream);
 hipError_t launch_monitor_finalize(const double* partials, int nblocks, double* out,
                                    hipStream_t stream);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);

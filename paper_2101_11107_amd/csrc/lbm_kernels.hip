@@ -166,6 +166,26 @@ hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_
     }
 }
 
+hipError_t launch_inplace_reverse(int storage, const StepArgs& a, hipStream_t stream) {
+    switch (storage) {
+        case 0: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 0>());
+        case 1: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 1>());
+        case 2: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 2>());
+        case 3: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 3>());
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_inplace_unstream(int storage, const StepArgs& a, hipStream_t stream) {
+    switch (storage) {
+        case 0: return launch_inplace_unstream_s(a, stream, std::integral_constant<int, 0>());
+        case 1: return launch_inplace_unstream_s(a, stream, std::integral_constant<int, 1>());
+        case 2: return launch_inplace_unstream_s(a, stream, std::integral_constant<int, 2>());
+        case 3: return launch_inplace_unstream_s(a, stream, std::integral_constant<int, 3>());
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_init(int storage, const StepArgs& a, const double* rho, const double* u,
                        hipStream_t stream) {
     LBM_DISPATCH(storage, init_t, a, rho, u, stream);

@@ -11,12 +11,53 @@ namespace {
 // One step over one domain.  XCD-aware order: hardware work-group b runs on
 // XCD (b % 8); each XCD gets a contiguous range of the node list, so
 // neighbouring rows share its L2.
-template <class S, bool MON, int FORM, bool PER, bool NT, bool CURVED>
+template <class S, bool MON, int FORM, bool PER, bool NT, bool CURVED, int IP = STREAM_PULL>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
     const int hb = blockIdx.x;
     const int lb = (hb & 7) * a.blocks_per_xcd + (hb >> 3);
     if (lb >= a.nblocks) return;
-    step_block<S, MON, FORM, PER, NT, BLOCK, CURVED>(a, lb);
+    step_block<S, MON, FORM, PER, NT, BLOCK, CURVED, IP>(a, lb);
+}
+
+// In-place streaming, pull layout <-> reversed layout: every node swaps its
+// slots a and abar (bit copies, no rounding).
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_inplace_reverse(StepArgs a) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    LBM_GLOBAL char* buf = (LBM_GLOBAL char*)a.fin;
+    const uint32_t own = node_off<S>((uint32_t)i);
+    S v[27];
+#pragma unroll
+    for (int al = 0; al < 27; ++al) v[al] = *(const LBM_GLOBAL S*)(buf + dir_off(al) + own);
+#pragma unroll
+    for (int al = 0; al < 27; ++al) *(LBM_GLOBAL S*)(buf + dir_off(26 - al) + own) = v[al];
+}
+
+// In-place streaming, streamed layout (a.fin) -> pull layout (a.fout): the
+// neighbour step's reads give f*_abar of this node for every direction al
+// (the values are only moved; the storage conversions are exact both ways).
+template <class S, bool PER>
+__global__ __launch_bounds__(BLOCK) void k_inplace_unstream(StepArgs a) {
+    using T = typename Traits<S>::T;
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    const LBM_GLOBAL char* fin = (const LBM_GLOBAL char*)a.fin;
+    LBM_GLOBAL char* fout = (LBM_GLOBAL char*)a.fout;
+    const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
+    const uint32_t own = node_off<S>((uint32_t)i);
+    T f[27];
+    uint32_t loc[27], wallmask = 0;
+    if (!(w & SPECIAL_BIT)) {
+        gather_fast<S, PER, false, STREAM_NEIGHBOUR>(fin, a, i, w, f, wallmask, loc);
+    } else {
+        const LBM_GLOBAL SpecialNode* sp = (const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT);
+        const uint32_t nonfluid = sp->wallmask | sp->linkmask;
+#pragma unroll
+        for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin, inplace_special_off<S>(sp, al, nonfluid, own));
+    }
+#pragma unroll
+    for (int al = 0; al < 27; ++al) stp<S>(fout + dir_off(26 - al), own, f[al]);
 }
 
 // FP32 steps of domains beyond the Infinity Cache run six work-groups per CU
@@ -27,13 +68,27 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
 // 6 x (26000 B + the monitor's static LDS) fits the CU's 160 KiB, 7 x does not.
 constexpr unsigned STEP_LDS_SIX_PER_CU = 26000;
 
-template <class S, bool MON, int FORM, bool NT, bool CURVED>
+template <class S, bool MON, int FORM, bool NT, bool CURVED, int IP = STREAM_PULL>
 hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
     const dim3 grid(8 * a.blocks_per_xcd), block(BLOCK);
     const unsigned lds = (NT && sizeof(S) == 4) ? STEP_LDS_SIX_PER_CU : 0u;
-    if (per) hipLaunchKernelGGL((k_step<S, MON, FORM, true, NT, CURVED>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_step<S, MON, FORM, false, NT, CURVED>), grid, block, lds, st, a);
+    if (per) hipLaunchKernelGGL((k_step<S, MON, FORM, true, NT, CURVED, IP>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_step<S, MON, FORM, false, NT, CURVED, IP>), grid, block, lds, st, a);
     return hipGetLastError();
+}
+
+// In-place steps keep their stores cached: the next step reads the same
+// buffer, which the Infinity Cache can hold where two buffers do not fit.
+template <class S, bool MON, int FORM>
+hipError_t step_inplace(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.inplace == STREAM_NEIGHBOUR) return step_per<S, MON, FORM, false, false, STREAM_NEIGHBOUR>(a, v.periodic_yz, st);
+    return step_per<S, MON, FORM, false, false, STREAM_LOCAL>(a, v.periodic_yz, st);
+}
+
+template <class S, bool MON>
+hipError_t step_form_inplace(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.srt2) return step_inplace<S, MON, 2>(a, v, st);
+    return v.rates_one ? step_inplace<S, MON, 1>(a, v, st) : step_inplace<S, MON, 0>(a, v, st);
 }
 
 template <class S, bool MON, bool NT, bool CURVED>
@@ -57,6 +112,10 @@ hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
 // 2-byte forms always store normally.
 template <class S>
 hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
+    if (v.inplace != STREAM_PULL) {
+        if (v.curved) return hipErrorInvalidValue;
+        return v.monitor ? step_form_inplace<S, true>(a, v, st) : step_form_inplace<S, false>(a, v, st);
+    }
     if constexpr (sizeof(S) >= 4) {
         if (v.stream_store) return step_nt<S, true>(a, v, st);
     }
@@ -80,6 +139,20 @@ hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream,
                          std::integral_constant<int, LBM_STEP_STORAGE>) {
     return step_t<LBM_STEP_T>(a, v, stream);
+}
+
+hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, LBM_STEP_STORAGE>) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_inplace_reverse<LBM_STEP_T>), dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, LBM_STEP_STORAGE>) {
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((a.n + BLOCK - 1) / BLOCK), block(BLOCK);
+    if (a.periodic & 6) hipLaunchKernelGGL((k_inplace_unstream<LBM_STEP_T, true>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((k_inplace_unstream<LBM_STEP_T, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
 }
 
 }  // namespace lbm

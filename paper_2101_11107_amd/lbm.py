@@ -28,7 +28,7 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2, LBM_BF16S: 2}
 EXPORTED = [
     "lbm_last_error", "lbm_create_domain", "lbm_create_domain_curved", "lbm_create_domain_ex", "lbm_wall_links",
     "lbm_device_bytes", "lbm_attach_device",
-    "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_collision", "lbm_set_inlet_womersley",
+    "lbm_fluid_count", "lbm_fluid_coords", "lbm_set_params", "lbm_set_collision", "lbm_set_streaming", "lbm_streaming_in_place", "lbm_set_inlet_womersley",
     "lbm_set_outlet_pressure", "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_moments",
     "lbm_average", "lbm_set_probes", "lbm_probe_count", "lbm_monitors", "lbm_read_populations", "lbm_get_state", "lbm_set_state",
     "lbm_inlet_profile", "lbm_destroy",
@@ -76,6 +76,8 @@ def load():
         "lbm_wall_links": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _P,
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_set_collision": ([_P, ctypes.c_int], ctypes.c_int),
+        "lbm_set_streaming": ([_P, ctypes.c_int], ctypes.c_int),
+        "lbm_streaming_in_place": ([_P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "lbm_set_probes": ([_P, _P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64], ctypes.c_int),
         "lbm_probe_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_device_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -222,6 +224,20 @@ COLLISION = {"chm_mrt": LBM_COLLISION_CHM_MRT, "srt2": LBM_COLLISION_SRT2}
 
 def lbm_set_collision(dom, kind) -> None:
     _check(load().lbm_set_collision(dom, COLLISION[kind] if isinstance(kind, str) else int(kind)))
+
+
+LBM_STREAM_PULL, LBM_STREAM_INPLACE, LBM_STREAM_AUTO = 0, 1, 2
+STREAMING = {"pull": LBM_STREAM_PULL, "inplace": LBM_STREAM_INPLACE, "auto": LBM_STREAM_AUTO}
+
+
+def lbm_set_streaming(dom, mode) -> None:
+    _check(load().lbm_set_streaming(dom, STREAMING[mode] if isinstance(mode, str) else int(mode)))
+
+
+def lbm_streaming_in_place(dom) -> bool:
+    v = ctypes.c_int(0)
+    _check(load().lbm_streaming_in_place(dom, ctypes.byref(v)))
+    return bool(v.value)
 
 
 def lbm_device_bytes(dom) -> int:
@@ -384,9 +400,13 @@ class Domain:
     bounce-back on those links, see ``lbm_create_domain_curved``).
     ``row_tile``: optional row-tile edge of the node order (see
     ``lbm_create_domain_ex``; the default order uses 8).
+    ``streaming``: "auto" (by size), "pull" (two buffers) or "inplace" (one
+    buffer updated in place), see ``lbm_set_streaming``; the results are the
+    same.
     """
 
-    def __init__(self, case, storage="f32", device="cuda:0", stream=None, wall_q=None, row_tile=None):
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None, wall_q=None, row_tile=None,
+                 streaming="auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required (the library has no CPU path)")
@@ -417,6 +437,7 @@ class Domain:
         lbm_attach_device(self.handle, self.view)
         lbm_set_params(self.handle, case.tau, case.rates, case.g)
         lbm_set_collision(self.handle, getattr(case, "collision", "chm_mrt"))
+        lbm_set_streaming(self.handle, streaming)
         if case.inlet is not None:
             i = case.inlet
             lbm_set_inlet_womersley(self.handle, i.axis, i.center, i.radius, i.G0, i.G1, i.omega)
@@ -436,6 +457,12 @@ class Domain:
 
     def step(self, n):
         lbm_step(self.handle, n)
+
+    def set_streaming(self, mode):
+        lbm_set_streaming(self.handle, mode)
+
+    def in_place(self) -> bool:
+        return lbm_streaming_in_place(self.handle)
 
     def coords(self):
         return lbm_fluid_coords(self.handle)

@@ -185,6 +185,51 @@ def test_curved_domain_validation_and_size():
         assert e.value.code == lbm.LBM_EINVAL
 
 
+def test_streaming_mode_validation():
+    """lbm_set_streaming takes its three modes before device memory is
+    attached; in-place streaming is refused for a domain with curved walls
+    (EINVAL), the automatic choice is not."""
+    lbm = _lbm()
+    case = synth.random_tiny_case(2, nx=11, ny=9, nz=8)
+    plain = lbm.lbm_create_domain(case.mask, case.periodic, lbm.LBM_F32, 0)
+    lbm.lbm_set_streaming(plain, "inplace")
+    assert lbm.lbm_streaming_in_place(plain)
+    lbm.lbm_set_streaming(plain, "pull")
+    assert not lbm.lbm_streaming_in_place(plain)
+    lbm.lbm_set_streaming(plain, "auto")
+    assert not lbm.lbm_streaming_in_place(plain)   # a few kB of populations: pull
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_streaming(plain, 3)
+    assert e.value.code == lbm.LBM_EINVAL
+    links = synth.wall_links(case.mask, case.periodic)
+    curved = lbm.lbm_create_domain_curved(case.mask, case.periodic, lbm.LBM_F32, links,
+                                          synth.random_wall_distances(links, 0), 0)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_streaming(curved, "inplace")
+    assert e.value.code == lbm.LBM_EINVAL
+    lbm.lbm_set_streaming(curved, "pull")
+    lbm.lbm_set_streaming(curved, "auto")
+    assert not lbm.lbm_streaming_in_place(curved)
+    lbm.lbm_destroy(plain)
+    lbm.lbm_destroy(curved)
+
+
+def test_streaming_auto_rule_at_512():
+    """The automatic choice at the 512^3 aneurysm: in place for FP32 (one
+    229 MB buffer fits the Infinity Cache, the pull scheme's two do not), pull
+    for the 2-byte forms (two 115 MB buffers fit) and for FP64 (one 458 MB
+    buffer does not); pull everywhere at 256^3."""
+    lbm = _lbm()
+    expect = {512: {lbm.LBM_F32: True, lbm.LBM_F16S: False, lbm.LBM_BF16S: False, lbm.LBM_F64: False},
+              256: {lbm.LBM_F32: False, lbm.LBM_F16S: False, lbm.LBM_BF16S: False, lbm.LBM_F64: False}}
+    for n, forms in expect.items():
+        case = synth.aneurysm_case(n, 0)
+        for storage, in_place in forms.items():
+            dom = lbm.lbm_create_domain(case.mask, 0, storage, 0)
+            assert lbm.lbm_streaming_in_place(dom) == in_place, (n, storage)
+            lbm.lbm_destroy(dom)
+
+
 def test_probe_arguments_need_device_memory_and_fluid_cells():
     lbm = _lbm()
     case = synth.random_tiny_case(2, nx=11, ny=9, nz=8)
