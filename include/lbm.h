@@ -195,7 +195,7 @@ int lbm_set_collision(lbm_domain* dom, int kind);
  * LBM_STREAM_AUTO (the default): in place where one population buffer is at
  * most 224 MiB and the two of the pull scheme are more (one buffer stays in
  * the 256 MB Infinity Cache, two do not), pull otherwise.  Measured at the
- * 512^3 aneurysm: FP32 (229 MB per buffer) steps 1.2-1.3 times faster in
+ * 512^3 aneurysm: FP32 (229 MB per buffer) steps about 1.2 times faster in
  * place; the 2-byte forms (two buffers of 115 MB fit) and FP64 (one buffer
  * of 458 MB does not) step faster with pull.  Never in place with curved
  * walls. */

@@ -387,7 +387,8 @@ __device__ __forceinline__ void gather_fast(const LBM_GLOBAL char* __restrict__ 
 // otherwise).
 // In-place streaming (IP = STREAM_NEIGHBOUR, STREAM_LOCAL) reads the same
 // values from the places the layout gives them (see STREAM_PULL); own is
-// node_off of this node, and loc receives the neighbour step's offsets.
+// node_off of this node, and loc receives the neighbour step's offsets.  The
+// node-local step's values (the node's own slots) are loaded by the caller.
 template <class S>
 __device__ __forceinline__ uint32_t inplace_special_off(const LBM_GLOBAL SpecialNode* __restrict__ sp, int al,
                                                         uint32_t nonfluid, uint32_t own) {
@@ -411,9 +412,8 @@ __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict
         } else if (IP == STREAM_NEIGHBOUR) {
             loc[al] = inplace_special_off<S>(sp, al, wm | lm, own);
             f[al] = ldp<S>(fin, loc[al]);
-        } else {
-            f[al] = ldp<S>(fin, own + dir_off(al));
         }
+        // STREAM_LOCAL: the caller has loaded the node's own slots into f
     }
     if (MON && wall_force && wm) {
 #pragma unroll
@@ -693,18 +693,22 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         T f[27];
         uint32_t wallmask = 0;
         double F[3] = {0.0, 0.0, 0.0}, qin = 0.0, qout = 0.0;
-        const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
-        const LBM_GLOBAL SpecialNode* sp = nullptr;
-        const bool curved = CURVED && a.crec != nullptr;
         // the node's own population offset without its direction part (curved
         // walls, in-place streaming)
         const uint32_t own0 = (CURVED || IP != STREAM_PULL) ? node_off<S>((uint32_t)i) : 0u;
+        if (IP == STREAM_LOCAL) {
+            // every node of the node-local step reads its own slots: issued
+            // before the descriptor says what kind of node this is
+#pragma unroll
+            for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin + dir_off(al), own0);
+        }
+        const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
+        const LBM_GLOBAL SpecialNode* sp = nullptr;
+        const bool curved = CURVED && a.crec != nullptr;
         // in-place neighbour step: where each direction was read
         uint32_t loc[27];
         if (!(w & SPECIAL_BIT)) {
             if (IP == STREAM_LOCAL) {
-#pragma unroll
-                for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin + dir_off(al), own0);
                 if (MON) gather_fast<S, PER, true, GATHER_WALL_BITS>(fin, a, i, w, f, wallmask, loc);
             } else {
                 gather_fast<S, PER, MON || CURVED, IP>(fin, a, i, w, f, wallmask, loc);

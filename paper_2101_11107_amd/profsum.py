@@ -53,22 +53,37 @@ def _one(pattern: str) -> str:
     return found[0]
 
 
-def step_stats(trace_dir: str) -> tuple:
+def step_stats(trace_dir: str, last: int = 0) -> tuple:
     """(rows [(name, calls, avg us, min us, max us)], call-weighted average us
-    of the step kernel, its launch count)."""
+    of the step kernel, its launch count).  last > 0: only the last `last`
+    step launches (per-dispatch trace), other kernels left out."""
     rows = []
-    with open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv"))) as fh:
-        for r in csv.DictReader(fh):
-            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-                         float(r["MaxNs"]) / 1e3))
+    if last > 0:
+        disp = []
+        with open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))) as fh:
+            for r in csv.DictReader(fh):
+                if STEP in r["Kernel_Name"]:
+                    disp.append((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+        disp = sorted(disp)[-last:]
+        by = {}
+        for _, name, us in disp:
+            by.setdefault(name, []).append(us)
+        rows = [(n, len(v), sum(v) / len(v), min(v), max(v)) for n, v in by.items()]
+    else:
+        with open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv"))) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                             float(r["MaxNs"]) / 1e3))
     steps = [r for r in rows if STEP in r[0]]
     calls = sum(r[1] for r in steps)
     avg = sum(r[1] * r[2] for r in steps) / calls
     return rows, avg, calls
 
 
-def counter(run_dir: str, name: str) -> tuple:
-    """(copy value, [step values]) of one counter, per dispatch (KiB)."""
+def counter(run_dir: str, name: str, last: int = 0) -> tuple:
+    """(copy value, [step values]) of one counter, per dispatch (KiB); last > 0:
+    the last `last` step dispatches only."""
     copy = 0.0
     steps = []
     with open(_one(os.path.join(run_dir, "**", "*counter_collection.csv"))) as fh:
@@ -79,8 +94,9 @@ def counter(run_dir: str, name: str) -> tuple:
             if COPY in r["Kernel_Name"]:
                 copy = max(copy, v)
             elif STEP in r["Kernel_Name"]:
-                steps.append(v)
-    return copy, steps
+                steps.append((int(r["Dispatch_Id"]), v))
+    steps = [v for _, v in sorted(steps)]
+    return copy, steps[-last:] if last > 0 else steps
 
 
 def fluid_nodes(trace_dir: str) -> tuple:
@@ -94,13 +110,13 @@ def fluid_nodes(trace_dir: str) -> tuple:
     raise ValueError("no bench result line in trace.log")
 
 
-def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str) -> str:
+def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str, last: int = 0) -> str:
     trace, fetch, write = (os.path.join(folder, k) for k in ("trace", "fetch", "write"))
-    rows, avg_us, calls = step_stats(trace)
+    rows, avg_us, calls = step_stats(trace, last)
     n, links = fluid_nodes(trace)
     moved_kib = copy_mib * 1024.0                     # the copy reads and writes this much
-    fc, fs = counter(fetch, "FETCH_SIZE")
-    wc, ws = counter(write, "WRITE_SIZE")
+    fc, fs = counter(fetch, "FETCH_SIZE", last)
+    wc, ws = counter(write, "WRITE_SIZE", last)
     f_scale, w_scale = moved_kib / fc, moved_kib / wc
     fetch_b = f_scale * sum(fs) / len(fs) * 1024.0
     write_b = w_scale * sum(ws) / len(ws) * 1024.0
@@ -112,8 +128,10 @@ def summarize(folder: str, storage: str, workload: str, copy_mib: int, cmd: str)
            f"# FETCH_SIZE command   : rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {cmd}",
            f"# WRITE_SIZE command   : rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {cmd}",
            f"# summary command      : python -m paper_2101_11107_amd.profsum --dir <dir> --storage {storage} "
-           f"--workload {workload} --copy-mib {copy_mib} --cmd \"<the bench command>\" --out <this file>",
-           "#", "# kernel statistics (kernel-trace run)"]
+           f"--workload {workload} --copy-mib {copy_mib}{f' --last {last}' if last else ''} "
+           f"--cmd \"<the bench command>\" --out <this file>",
+           "#", "# kernel statistics (kernel-trace run" +
+           (f"; the last {last} step launches, after the run's untimed spin-up steps)" if last else ")")]
     for name, c, a, lo, hi in sorted(rows, key=lambda r: -r[1] * r[2])[:8]:
         short = name.replace("(anonymous namespace)::", "").replace("(lbm::StepArgs)", "")
         out.append(f"#   {short[:78]:78s} calls {c:5d}  avg {a:9.3f} us  min {lo:9.3f}  max {hi:9.3f}")
@@ -246,6 +264,8 @@ def main():
     ap.add_argument("--pmc-run", action="append", default=[],
                     help="extra counter run as subfolder=rocprofv3 options (repeatable)")
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--last", type=int, default=0,
+                    help="step kernel: average only the last N launches (the bench's warm-up and timed steps)")
     ap.add_argument("--conv-flops", default=None,
                     help="train_steps,crop_coarse_voxels,forwards,grid_coarse_voxels: add the convolution efficiency")
     ap.add_argument("--cmd", required=True)
@@ -258,7 +278,7 @@ def main():
             ts, cv, fw, gv = (int(v) for v in a.conv_flops.split(","))
             text += "\n".join(conv_efficiency(os.path.join(a.dir, "trace"), ts, cv, fw, gv)) + "\n"
     else:
-        text = summarize(a.dir, a.storage, a.workload, a.copy_mib, a.cmd)
+        text = summarize(a.dir, a.storage, a.workload, a.copy_mib, a.cmd, a.last)
     with open(a.out, "w") as fh:
         fh.write(text)
     print(text, end="")
