@@ -764,6 +764,10 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     if (((uintptr_t)dev_ptr & 255u) != 0) return fail(LBM_EINVAL, "device buffer must be 256-byte aligned");
     d->dev = (char*)dev_ptr;
     d->drop_graphs();
+    // new memory holds no state: the pull layout until the next initialisation
+    d->cur = 0;
+    d->pop_flip = 0;
+    d->layout = LAYOUT_PULL;
     hipStream_t st = d->stream;
     HIP_TRY(lbm::launch_fill_zero(d->dev, d->dev_bytes, st), "clearing device memory");
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_node, d->node_words.data(), d->node_words.size() * 4,
