@@ -192,13 +192,14 @@ int lbm_set_collision(lbm_domain* dom, int kind);
  * moves them again.  Memory use is unchanged.  May be called at any time.
  * EINVAL for an unknown mode, or LBM_STREAM_INPLACE on a domain with curved
  * walls (lbm_create_domain_curved).
- * LBM_STREAM_AUTO (the default): in place where one population buffer is at
- * most 224 MiB and the two of the pull scheme are more (one buffer stays in
- * the 256 MB Infinity Cache, two do not), pull otherwise.  Measured at the
- * 512^3 aneurysm: FP32 (229 MB per buffer) steps about 1.2 times faster in
- * place; the 2-byte forms (two buffers of 115 MB fit) and FP64 (one buffer
- * of 458 MB does not) step faster with pull.  Never in place with curved
- * walls. */
+ * LBM_STREAM_AUTO (the default): in place for 4- and 8-byte populations
+ * where the two buffers of the pull scheme exceed 192 MiB (they no longer
+ * stay in the 256 MB Infinity Cache) and one buffer is at most 320 MiB; pull
+ * otherwise.  Measured on the synthetic aneurysm at 256^3-512^3: in place
+ * steps FP32 1.15-1.23 times faster at 105-218 MiB per buffer and FP64 1.16
+ * and 1.07 times at 209 and 293 MiB; FP64 at 437 MiB and the 2-byte forms
+ * (whose step is bound by vector instructions more than by memory) step
+ * faster with pull.  Never in place with curved walls. */
 enum { LBM_STREAM_PULL = 0, LBM_STREAM_INPLACE = 1, LBM_STREAM_AUTO = 2 };
 int lbm_set_streaming(lbm_domain* dom, int mode);
 

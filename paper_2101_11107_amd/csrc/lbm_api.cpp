@@ -248,8 +248,11 @@ int prepare_links(lbm_domain* d) {
 bool lbm_domain::use_inplace() const {
     if (!crec.empty() || stream_mode == LBM_STREAM_PULL) return false;
     if (stream_mode == LBM_STREAM_INPLACE) return true;
-    // one buffer fits the Infinity Cache, the two of the pull scheme do not
-    return pop_bytes <= lbm_host::INPLACE_MAX_BYTES && 2 * pop_bytes > lbm_host::INPLACE_MAX_BYTES;
+    // 4- and 8-byte populations whose two pull buffers no longer stay in the
+    // Infinity Cache, while one buffer is small enough for it to serve part
+    // of the in-place traffic
+    return storage_bytes(storage) >= 4 && 2 * pop_bytes > lbm_host::STREAM_STORE_BYTES &&
+           pop_bytes <= lbm_host::INPLACE_MAX_BYTES;
 }
 
 namespace lbm_host {

@@ -22,10 +22,12 @@ constexpr int GRAPH_STEPS = 16;   // even, so a replay returns to the same buffe
 // Population working sets above this size do not stay in the 256 MB Infinity
 // Cache; there streaming (non-temporal) stores are faster.
 constexpr size_t STREAM_STORE_BYTES = (size_t)192 << 20;
-// LBM_STREAM_AUTO streams in place where one population buffer is at most
-// this size and the two of the pull scheme are more: one buffer then stays in
-// the 256 MB Infinity Cache, two do not.
-constexpr size_t INPLACE_MAX_BYTES = (size_t)224 << 20;
+// LBM_STREAM_AUTO streams 4- and 8-byte populations in place where the two
+// buffers of the pull scheme exceed STREAM_STORE_BYTES and one buffer is at
+// most this size (measured at the aneurysm: in place gains 15-23 % for FP32
+// at 105-218 MiB per buffer, 16 % and 7 % for FP64 at 209 and 293 MiB, and
+// loses 11 % for FP64 at 437 MiB; the 2-byte forms lose 10 % at 52-109 MiB).
+constexpr size_t INPLACE_MAX_BYTES = (size_t)320 << 20;
 
 }  // namespace lbm_host
 

@@ -214,13 +214,14 @@ def test_streaming_mode_validation():
     lbm.lbm_destroy(curved)
 
 
-def test_streaming_auto_rule_at_512():
-    """The automatic choice at the 512^3 aneurysm: in place for FP32 (one
-    229 MB buffer fits the Infinity Cache, the pull scheme's two do not), pull
-    for the 2-byte forms (two 115 MB buffers fit) and for FP64 (one 458 MB
-    buffer does not); pull everywhere at 256^3."""
+def test_streaming_auto_rule():
+    """The automatic choice on the aneurysm geometries: in place for FP32 at
+    400^3 and 512^3 (105 and 218 MiB per buffer) and FP64 at 400^3 (209 MiB);
+    pull for FP64 at 512^3 (437 MiB per buffer), for every form at 256^3
+    (the two buffers stay in the Infinity Cache) and for the 2-byte forms."""
     lbm = _lbm()
     expect = {512: {lbm.LBM_F32: True, lbm.LBM_F16S: False, lbm.LBM_BF16S: False, lbm.LBM_F64: False},
+              400: {lbm.LBM_F32: True, lbm.LBM_F16S: False, lbm.LBM_F64: True},
               256: {lbm.LBM_F32: False, lbm.LBM_F16S: False, lbm.LBM_BF16S: False, lbm.LBM_F64: False}}
     for n, forms in expect.items():
         case = synth.aneurysm_case(n, 0)
