@@ -195,3 +195,36 @@ def test_batch_after_inplace_steps():
             d.close()
     for fa, fb in zip(*runs):
         assert _same_bits(fa, fb)
+
+
+def test_inplace_parameter_changes_mid_run():
+    """Relaxation, collision operator, inlet and outlet changed between steps
+    (each drops the captured graphs) while the buffer is in either in-place
+    layout: equal to the same sequence with pull."""
+    import torch
+    from paper_2101_11107_amd import lbm
+    print("case aneurysm128 f32 inplace parameter changes", flush=True)
+    case = synth.aneurysm_case(128, seed=0)
+    a, b = _pair(case, "f32")
+    seq = [
+        (17, lambda d: lbm.lbm_set_params(d.handle, case.tau * 1.05, (1.0, 1.2, 0.9, 1.0), case.g)),
+        (16, lambda d: lbm.lbm_set_collision(d.handle, "srt2")),
+        (33, lambda d: lbm.lbm_set_outlet_pressure(d.handle, case.rho_out * 1.0005)),
+        (5, lambda d: lbm.lbm_set_collision(d.handle, "chm_mrt")),
+        (19, None),
+    ]
+    if case.inlet is not None:
+        i = case.inlet
+        seq.insert(2, (8, lambda d: lbm.lbm_set_inlet_womersley(d.handle, i.axis, i.center, i.radius, i.G0 * 1.1,
+                                                                 i.G1, i.omega)))
+    for steps, change in seq:
+        for d in (a, b):
+            d.step(steps)
+            if change is not None:
+                change(d)
+    fa, fb = a.populations(), b.populations()
+    torch.cuda.synchronize()
+    assert _same_bits(fa, fb)
+    assert np.array_equal(np.asarray(a.monitors()), np.asarray(b.monitors()))
+    a.close()
+    b.close()
