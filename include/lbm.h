@@ -189,9 +189,11 @@ int lbm_set_collision(lbm_domain* dom, int kind);
  * Readers of the state (lbm_moments, lbm_average, lbm_read_populations,
  * lbm_get_state) and batches first move the populations back to the pull
  * layout (one extra pass, on the domain's stream); the next in-place step
- * moves them again.  Memory use is unchanged.  May be called at any time.
- * EINVAL for an unknown mode, or LBM_STREAM_INPLACE on a domain with curved
- * walls (lbm_create_domain_curved).
+ * moves them again.  With curved walls (lbm_create_domain_curved) the
+ * q >= 1/2 rule needs the node's own f*_a(x), whose slot another node
+ * rewrites in place; the domain keeps it per wall link (one population per
+ * weight record, part of lbm_device_bytes).  May be called at any time.
+ * EINVAL for an unknown mode.
  * LBM_STREAM_AUTO (the default): in place for 4- and 8-byte populations
  * where the two buffers of the pull scheme exceed 192 MiB (they no longer
  * stay in the 256 MB Infinity Cache) and one buffer is at most 320 MiB; pull
@@ -199,7 +201,7 @@ int lbm_set_collision(lbm_domain* dom, int kind);
  * steps FP32 1.15-1.23 times faster at 105-218 MiB per buffer and FP64 1.16
  * and 1.07 times at 209 and 293 MiB; FP64 at 437 MiB and the 2-byte forms
  * (whose step is bound by vector instructions more than by memory) step
- * faster with pull.  Never in place with curved walls. */
+ * faster with pull. */
 enum { LBM_STREAM_PULL = 0, LBM_STREAM_INPLACE = 1, LBM_STREAM_AUTO = 2 };
 int lbm_set_streaming(lbm_domain* dom, int mode);
 

@@ -26,6 +26,11 @@ FLAGS = [
     # packed FP32 instructions stay off (hipcc warns that the host pass does not
     # know the feature; that warning is harmless)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiplies fuse into adds only within one source expression: with
+    # fusion across statements, a product reused elsewhere in one variant of
+    # a kernel (say, by the monitors) stays unfused there and fused in
+    # another, and the variants would round differently
+    "-ffp-contract=on",
 ]
 
 

@@ -112,6 +112,7 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     a.link_coef = (const double*)(base + d->off_lcoef);
     a.link_add = (double*)(base + d->off_ladd);
     a.crec = d->crec.empty() ? nullptr : base + d->off_crec;
+    a.cside = d->crec.empty() ? nullptr : base + d->off_cside;
     a.crec_base = (const uint32_t*)(base + d->off_cbase);
     a.tcount = (int64_t*)(base + d->off_tcount);
     a.trig = (double*)(base + d->off_trig);
@@ -246,7 +247,7 @@ int prepare_links(lbm_domain* d) {
 }  // namespace lbm_host
 
 bool lbm_domain::use_inplace() const {
-    if (!crec.empty() || stream_mode == LBM_STREAM_PULL) return false;
+    if (stream_mode == LBM_STREAM_PULL) return false;
     if (stream_mode == LBM_STREAM_INPLACE) return true;
     // 4- and 8-byte populations whose two pull buffers no longer stay in the
     // Infinity Cache, while one buffer is small enough for it to serve part
@@ -262,7 +263,7 @@ int sync_pull(lbm_domain* d) {
     lbm::StepArgs a = make_args(d);
     if (d->layout == LAYOUT_REVERSED) {
         // slot reversal in place
-        HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, d->stream), "in-place layout");
+        HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, false, d->stream), "in-place layout");
     } else {
         // the streamed layout is a permutation of the post-collision values:
         // gathered into the other buffer, which becomes the one read next
@@ -332,7 +333,8 @@ int build_graph(lbm_domain* d) {
 // Pull layout -> reversed layout, in place (the first in-place step reads it).
 int enter_inplace(lbm_domain* d) {
     const lbm::StepArgs a = make_args(d);
-    HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, d->stream), "in-place layout");
+    // curved walls: the blend's own values start from the pull layout
+    HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, !d->crec.empty(), d->stream), "in-place layout");
     d->layout = LAYOUT_REVERSED;
     return LBM_OK;
 }
@@ -633,6 +635,8 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->off_probe = take(lbm::MAX_PROBES * sizeof(int32_t));
         d->off_crec = take(std::max<size_t>(1, d->crec.size()) * (storage == LBM_F64 ? 8 : 4));
         d->off_cbase = take(std::max<size_t>(1, d->crec_base.size()) * sizeof(uint32_t));
+        // curved walls streamed in place: the own value of each wall link
+        d->off_cside = take(std::max<size_t>(1, d->crec.size()) * sb);
         d->dev_bytes = off;
     } catch (const std::bad_alloc&) {
         delete d;
@@ -872,8 +876,6 @@ int lbm_set_streaming(lbm_domain* d, int mode) {
     if (!d) return fail(LBM_EINVAL, "NULL argument");
     if (mode != LBM_STREAM_PULL && mode != LBM_STREAM_INPLACE && mode != LBM_STREAM_AUTO)
         return fail(LBM_EINVAL, "unknown streaming mode");
-    if (mode == LBM_STREAM_INPLACE && !d->crec.empty())
-        return fail(LBM_EINVAL, "in-place streaming does not take curved walls");
     d->stream_mode = mode;
     // leaving in-place streaming: the pull step reads the pull layout
     if (!d->use_inplace() && d->dev) return sync_pull(d);

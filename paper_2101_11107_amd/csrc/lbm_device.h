@@ -63,6 +63,10 @@ template <> struct Traits<__bf16> {
     __device__ static __bf16 store(T v) { return (__bf16)v; }        // round to nearest even
 };
 
+// Fused multiply-add in the arithmetic type (one rounding).
+__device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Load / store of one population at a byte offset from a uniform base.
 // Population and table pointers reach the step as kernel arguments or, for
 // batched stepping, from an argument table in memory; the explicit global
@@ -461,11 +465,17 @@ __device__ __forceinline__ void gather_special(const LBM_GLOBAL char* __restrict
 // halves, each issuing its record and second-value loads together; the first
 // half's loads go out with the gather's.  With MON, the
 // wall force of each link, (f*_abar(x) + f_al(x, t+1)) c_abar in full
-// populations, is subtracted from F.
-template <class S, bool MON>
+// populations, is subtracted from F.  Streamed in place (IP != STREAM_PULL)
+// the node's own f*_al(x) sits in a slot another node rewrites during the
+// step, so it comes from the record's entry of a.cside instead, which
+// curved_side_store refreshes after the collision.
+template <class S, bool MON, int IP = STREAM_PULL>
 __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__ fin, const StepArgs& a, int i,
                                              uint32_t own0, uint32_t wallmask, typename Traits<S>::T (&f)[27],
                                              double (&F)[3]) {
+    // rounding pinned (one fused multiply-add per blend, no other fusion), so
+    // that every kernel built from this body rounds alike
+#pragma clang fp contract(off)
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
     const LBM_GLOBAL T* __restrict__ rec = (const LBM_GLOBAL T*)a.crec;
@@ -492,7 +502,8 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
                 cum += (uint32_t)__popcll(B[k]);
                 if (wl) {
                     r[k] = rec[idx];
-                    f2[k] = ldp<S>(fin + dir_off(al), own0);
+                    if (IP == STREAM_PULL) f2[k] = ldp<S>(fin + dir_off(al), own0);
+                    else f2[k] = Traits<S>::cvt(((const LBM_GLOBAL S*)a.cside)[idx]);
                 }
             }
         }
@@ -503,7 +514,7 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
             const T own = f[al];
             const bool hi = r[k] < T(0);
             const T w0 = hi ? -r[k] : r[k];
-            const T v = w0 * own + (T(1) - w0) * (hi ? f2[k] : f[26 - al]);
+            const T v = fma_rn(w0, own, (T(1) - w0) * (hi ? f2[k] : f[26 - al]));
             f[al] = v;
             if (MON) {
                 // this lane's bit of the ballot (not of wallmask: reusing that
@@ -526,6 +537,29 @@ __device__ __forceinline__ void curved_blend(const LBM_GLOBAL char* __restrict__
         F[0] -= (double)fx;
         F[1] -= (double)fy;
         F[2] -= (double)fz;
+    }
+}
+
+// Curved walls streamed in place: after the collision, each wall link's record
+// entry of a.cside takes the node's post-collision f*_al(x) (in the storage
+// type, rounded as the population store rounds it), for the next step's
+// blend.  Records in the blend's order: per 64-node chunk, then direction
+// (al = 0..26 without 13), then node.
+template <class S>
+__device__ __forceinline__ void curved_side_store(const StepArgs& a, int i, uint32_t wallmask,
+                                                  const typename Traits<S>::T (&f)[27]) {
+    LBM_GLOBAL S* side = (LBM_GLOBAL S*)a.cside;
+    const int chunk = __builtin_amdgcn_readfirstlane(i / CREC_CHUNK);
+    uint32_t cum = ((const LBM_GLOBAL uint32_t*)a.crec_base)[chunk];
+#pragma unroll
+    for (int al = 0; al < 27; ++al) {
+        if (al == 13) continue;
+        const bool wl = (wallmask >> al) & 1u;
+        const unsigned long long B = __ballot(wl);
+        if (B == 0ull) continue;
+        const uint32_t idx = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, cum));
+        cum += (uint32_t)__popcll(B);
+        if (wl) side[idx] = Traits<S>::store(f[al]);
     }
 }
 
@@ -679,7 +713,6 @@ __device__ __forceinline__ void collide(T (&f)[27], const StepArgs& a, T& ux, T&
 // arithmetic as the pull step).
 template <class S, bool MON, int FORM, bool PER, bool NT, int BS, bool CURVED, int IP = STREAM_PULL>
 __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
-    static_assert(IP == STREAM_PULL || !CURVED, "in-place streaming has no curved walls");
     using T = typename Traits<S>::T;
     constexpr uint32_t SZ = sizeof(S);
     const int i = lb * BS + threadIdx.x;
@@ -709,7 +742,7 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         uint32_t loc[27];
         if (!(w & SPECIAL_BIT)) {
             if (IP == STREAM_LOCAL) {
-                if (MON) gather_fast<S, PER, true, GATHER_WALL_BITS>(fin, a, i, w, f, wallmask, loc);
+                if (MON || curved) gather_fast<S, PER, true, GATHER_WALL_BITS>(fin, a, i, w, f, wallmask, loc);
             } else {
                 gather_fast<S, PER, MON || CURVED, IP>(fin, a, i, w, f, wallmask, loc);
             }
@@ -721,7 +754,7 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
         }
         if (curved) {
             // every wall link has a record (r = 1: halfway)
-            if (__ballot(wallmask != 0u)) curved_blend<S, MON>(fin, a, i, own0, wallmask, f, F);
+            if (__ballot(wallmask != 0u)) curved_blend<S, MON, IP>(fin, a, i, own0, wallmask, f, F);
         } else if (MON && wallmask) {
             T fx = T(0), fy = T(0), fz = T(0);
 #pragma unroll
@@ -774,6 +807,9 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
             mon[6] = F[2];
             mon[7] = qin;
             mon[8] = qout;
+        }
+        if (IP != STREAM_PULL && curved) {
+            if (__ballot(wallmask != 0u)) curved_side_store<S>(a, i, wallmask, f);
         }
         if (IP == STREAM_PULL) {
 #pragma unroll

@@ -101,6 +101,8 @@ struct StepArgs {
     double* link_add;            // [nlinks]
     const void* crec;            // curved-wall weights, or null (halfway walls)
     const uint32_t* crec_base;   // [npad / CREC_CHUNK] first record of each 64-node chunk
+    void* cside;                 // curved walls streamed in place: per record, the node's own
+                                 // post-collision f*_alpha of the last step (storage type)
     int64_t* tcount;             // [2] time counters (read slot tin, write slot tin ^ 1)
     double* trig;                // [2][2] (cos, sin)(omega t), slot t & 1
     double* partials;            // [nblocks][MON_WORDS] monitor partials
@@ -178,10 +180,10 @@ hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, s
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 1>);
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 2>);
 hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream, std::integral_constant<int, 3>);
-hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 0>);
-hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 1>);
-hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 2>);
-hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 3>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, bool fill_side, hipStream_t stream, std::integral_constant<int, 0>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, bool fill_side, hipStream_t stream, std::integral_constant<int, 1>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, bool fill_side, hipStream_t stream, std::integral_constant<int, 2>);
+hipError_t launch_inplace_reverse_s(const StepArgs& a, bool fill_side, hipStream_t stream, std::integral_constant<int, 3>);
 hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 0>);
 hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 1>);
 hipError_t launch_inplace_unstream_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, 2>);
@@ -192,9 +194,11 @@ hipError_t launch_moments(int storage, const StepArgs& a, double* rho, double* u
                           int avg_mode, double avg_count, hipStream_t stream);
 hipError_t launch_read_populations(int storage, const StepArgs& a, double* out, hipStream_t stream);
 // In-place streaming layouts to and from the pull layout (lbm_step.hip):
-// reverse swaps every node's slots a and abar of a.fin in place (pull <-> R);
-// unstream writes the pull layout of the S state in a.fin into a.fout.
-hipError_t launch_inplace_reverse(int storage, const StepArgs& a, hipStream_t stream);
+// reverse swaps every node's slots a and abar of a.fin in place (pull <-> R;
+// fill_side, from the pull layout: also copy each curved-wall link's own
+// f*_alpha into a.cside); unstream writes the pull layout of the S state in
+// a.fin into a.fout.
+hipError_t launch_inplace_reverse(int storage, const StepArgs& a, bool fill_side, hipStream_t stream);
 hipError_t launch_inplace_unstream(int storage, const StepArgs& a, hipStream_t stream);
 hipError_t launch_monitor_finalize(const double* partials, int nblocks, double* out,
                                    hipStream_t stream);

@@ -166,12 +166,12 @@ hipError_t launch_step(int storage, const StepArgs& a, StepVariant v, hipStream_
     }
 }
 
-hipError_t launch_inplace_reverse(int storage, const StepArgs& a, hipStream_t stream) {
+hipError_t launch_inplace_reverse(int storage, const StepArgs& a, bool fill_side, hipStream_t stream) {
     switch (storage) {
-        case 0: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 0>());
-        case 1: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 1>());
-        case 2: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 2>());
-        case 3: return launch_inplace_reverse_s(a, stream, std::integral_constant<int, 3>());
+        case 0: return launch_inplace_reverse_s(a, fill_side, stream, std::integral_constant<int, 0>());
+        case 1: return launch_inplace_reverse_s(a, fill_side, stream, std::integral_constant<int, 1>());
+        case 2: return launch_inplace_reverse_s(a, fill_side, stream, std::integral_constant<int, 2>());
+        case 3: return launch_inplace_reverse_s(a, fill_side, stream, std::integral_constant<int, 3>());
         default: return hipErrorInvalidValue;
     }
 }

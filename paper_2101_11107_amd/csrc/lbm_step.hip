@@ -20,8 +20,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a) {
 }
 
 // In-place streaming, pull layout <-> reversed layout: every node swaps its
-// slots a and abar (bit copies, no rounding).
-template <class S>
+// slots a and abar (bit copies, no rounding).  FILL (entering from the pull
+// layout with curved walls): each wall link's record entry of a.cside takes
+// the node's own f*_al(x), in the record order of curved_blend.
+template <class S, bool PER, bool FILL>
 __global__ __launch_bounds__(BLOCK) void k_inplace_reverse(StepArgs a) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= a.n) return;
@@ -30,6 +32,32 @@ __global__ __launch_bounds__(BLOCK) void k_inplace_reverse(StepArgs a) {
     S v[27];
 #pragma unroll
     for (int al = 0; al < 27; ++al) v[al] = *(const LBM_GLOBAL S*)(buf + dir_off(al) + own);
+    if (FILL) {
+        const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
+        uint32_t wallmask = 0, loc[27];
+        if (!(w & SPECIAL_BIT)) {
+            typename Traits<S>::T unused[27];
+            gather_fast<S, PER, true, GATHER_WALL_BITS>(buf, a, i, w, unused, wallmask, loc);
+        } else {
+            wallmask = ((const LBM_GLOBAL SpecialNode*)a.spec + (w & ~SPECIAL_BIT))->wallmask;
+        }
+        if (__ballot(wallmask != 0u)) {
+            LBM_GLOBAL S* side = (LBM_GLOBAL S*)a.cside;
+            const int chunk = __builtin_amdgcn_readfirstlane(i / CREC_CHUNK);
+            uint32_t cum = ((const LBM_GLOBAL uint32_t*)a.crec_base)[chunk];
+#pragma unroll
+            for (int al = 0; al < 27; ++al) {
+                if (al == 13) continue;
+                const bool wl = (wallmask >> al) & 1u;
+                const unsigned long long B = __ballot(wl);
+                if (B == 0ull) continue;
+                const uint32_t idx =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, cum));
+                cum += (uint32_t)__popcll(B);
+                if (wl) side[idx] = v[al];
+            }
+        }
+    }
 #pragma unroll
     for (int al = 0; al < 27; ++al) *(LBM_GLOBAL S*)(buf + dir_off(26 - al) + own) = v[al];
 }
@@ -79,16 +107,22 @@ hipError_t step_per(const StepArgs& a, bool per, hipStream_t st) {
 
 // In-place steps keep their stores cached: the next step reads the same
 // buffer, which the Infinity Cache can hold where two buffers do not fit.
-template <class S, bool MON, int FORM>
+template <class S, bool MON, int FORM, bool CURVED>
 hipError_t step_inplace(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if (v.inplace == STREAM_NEIGHBOUR) return step_per<S, MON, FORM, false, false, STREAM_NEIGHBOUR>(a, v.periodic_yz, st);
-    return step_per<S, MON, FORM, false, false, STREAM_LOCAL>(a, v.periodic_yz, st);
+    if (v.inplace == STREAM_NEIGHBOUR)
+        return step_per<S, MON, FORM, false, CURVED, STREAM_NEIGHBOUR>(a, v.periodic_yz, st);
+    return step_per<S, MON, FORM, false, CURVED, STREAM_LOCAL>(a, v.periodic_yz, st);
 }
 
-template <class S, bool MON>
+template <class S, bool MON, bool CURVED>
 hipError_t step_form_inplace(const StepArgs& a, StepVariant v, hipStream_t st) {
-    if (v.srt2) return step_inplace<S, MON, 2>(a, v, st);
-    return v.rates_one ? step_inplace<S, MON, 1>(a, v, st) : step_inplace<S, MON, 0>(a, v, st);
+    if (v.srt2) return step_inplace<S, MON, 2, CURVED>(a, v, st);
+    return v.rates_one ? step_inplace<S, MON, 1, CURVED>(a, v, st) : step_inplace<S, MON, 0, CURVED>(a, v, st);
+}
+
+template <class S, bool CURVED>
+hipError_t step_mon_inplace(const StepArgs& a, StepVariant v, hipStream_t st) {
+    return v.monitor ? step_form_inplace<S, true, CURVED>(a, v, st) : step_form_inplace<S, false, CURVED>(a, v, st);
 }
 
 template <class S, bool MON, bool NT, bool CURVED>
@@ -113,8 +147,8 @@ hipError_t step_nt(const StepArgs& a, StepVariant v, hipStream_t st) {
 template <class S>
 hipError_t step_t(const StepArgs& a, StepVariant v, hipStream_t st) {
     if (v.inplace != STREAM_PULL) {
-        if (v.curved) return hipErrorInvalidValue;
-        return v.monitor ? step_form_inplace<S, true>(a, v, st) : step_form_inplace<S, false>(a, v, st);
+        if (v.curved && a.cside == nullptr) return hipErrorInvalidValue;
+        return v.curved ? step_mon_inplace<S, true>(a, v, st) : step_mon_inplace<S, false>(a, v, st);
     }
     if constexpr (sizeof(S) >= 4) {
         if (v.stream_store) return step_nt<S, true>(a, v, st);
@@ -141,9 +175,14 @@ hipError_t launch_step_s(const StepArgs& a, StepVariant v, hipStream_t stream,
     return step_t<LBM_STEP_T>(a, v, stream);
 }
 
-hipError_t launch_inplace_reverse_s(const StepArgs& a, hipStream_t stream, std::integral_constant<int, LBM_STEP_STORAGE>) {
+hipError_t launch_inplace_reverse_s(const StepArgs& a, bool fill_side, hipStream_t stream,
+                                    std::integral_constant<int, LBM_STEP_STORAGE>) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_inplace_reverse<LBM_STEP_T>), dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, a);
+    if (fill_side && (a.cside == nullptr || a.crec == nullptr)) return hipErrorInvalidValue;
+    const dim3 grid((a.n + BLOCK - 1) / BLOCK), block(BLOCK);
+    if (!fill_side) hipLaunchKernelGGL((k_inplace_reverse<LBM_STEP_T, false, false>), grid, block, 0, stream, a);
+    else if (a.periodic & 6) hipLaunchKernelGGL((k_inplace_reverse<LBM_STEP_T, true, true>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((k_inplace_reverse<LBM_STEP_T, false, true>), grid, block, 0, stream, a);
     return hipGetLastError();
 }
 

@@ -37,9 +37,9 @@ def _same_bits(x, y):
     return x.shape == y.shape and torch.equal(x.view(torch.int64), y.view(torch.int64))
 
 
-def _run_and_compare(case, storage, checkpoints=CHECKPOINTS):
+def _run_and_compare(case, storage, checkpoints=CHECKPOINTS, **kw):
     import torch
-    a, b = _pair(case, storage)
+    a, b = _pair(case, storage, **kw)
     done = 0
     for c in checkpoints:
         a.step(c - done)
@@ -228,3 +228,40 @@ def test_inplace_parameter_changes_mid_run():
     assert np.array_equal(np.asarray(a.monitors()), np.asarray(b.monitors()))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("seed", [0, 2])
+def test_inplace_curved_equals_pull(storage, seed):
+    """Curved walls with random wall distances (both rules of the blend, open
+    links and periodic axes on the same tiny masks): the in-place run keeps
+    each link's own value aside and equals the pull run bitwise."""
+    print(f"case tiny{seed} curved {storage} inplace", flush=True)
+    case = synth.random_tiny_case(seed, nx=31, ny=9, nz=8)
+    links = synth.wall_links(case.mask, case.periodic)
+    q = synth.random_wall_distances(links, seed)
+    _run_and_compare(case, storage, wall_q=(links, q))
+
+
+def test_inplace_curved_equals_pull_aneurysm():
+    print("case aneurysm128 curved f32 inplace", flush=True)
+    case = synth.aneurysm_case(128, seed=0)
+    links = synth.wall_links(case.mask, case.periodic)
+    _run_and_compare(case, "f32", checkpoints=(16, 33, 64), wall_q=(links, synth.wall_distances(case, links)))
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_inplace_curved_matches_oracle_f64(seed):
+    from paper_2101_11107_amd import lbm
+    case = synth.random_tiny_case(seed, nx=11, ny=9, nz=8)
+    links = synth.wall_links(case.mask, case.periodic)
+    q = synth.random_wall_distances(links, seed)
+    for steps in (21, 20):
+        print(f"case tiny{seed} curved f64 inplace {steps} steps vs oracle", flush=True)
+        dom = lbm.Domain(case, storage="f64", streaming="inplace", wall_q=(links, q))
+        dom.init()
+        dom.step(steps)
+        f = dom.populations().cpu().numpy().T.copy()[oracle_order(dom.coords(), case.mask)]
+        dom.close()
+        _, ref, _, _ = oracle_post(case, steps, wall_q=(links, q))
+        assert np.max(np.abs(f - ref)) < 1e-13
