@@ -98,11 +98,12 @@ def run_form(torch, lbm, case, storage, warmup, steps, want_u=False, wall_q=None
     return out
 
 
-def curved_bench(torch, lbm, case, storage, warmup, steps, plain):
+def curved_bench(torch, lbm, case, storage, warmup, steps, plain, plain_pull):
     """Curved walls (interpolated bounce-back with the exact wall distance on
     every wall link of the geometry): the step rate against the plain halfway
-    form of the same run, and the pipe Poiseuille error of both wall rules
-    against the start-up series at R = 5, 10, 20 (FP64, 20 R^2 steps)."""
+    form of the same run with the same streaming pattern (and against the
+    halfway pull run), and the pipe Poiseuille error of both wall rules against
+    the start-up series at R = 5, 10, 20 (FP64, 20 R^2 steps)."""
     import numpy as np
     import scipy.special
     import synth
@@ -111,8 +112,9 @@ def curved_bench(torch, lbm, case, storage, warmup, steps, plain):
     r = run_form(torch, lbm, case, storage, warmup, steps, want_u=True, wall_q=(links, q))
     rf = roofline(r["n"], r["ms_per_step"], storage, None)
     out = {"workload": case.name.split("_")[0] + "_curved_walls", "storage": storage, "wall_links": int(len(links)),
-           "mlups": round(r["mlups"], 1), "roofline_frac": rf["frac"],
-           "rate_vs_halfway": round(r["mlups"] / plain["mlups"], 3)}
+           "mlups": round(r["mlups"], 1), "roofline_frac": rf["frac"], "streaming": r["streaming"],
+           "rate_vs_halfway": round(r["mlups"] / plain["mlups"], 3),
+           "rate_vs_halfway_pull": round(r["mlups"] / plain_pull["mlups"], 3)}
     if "u" in plain:
         out["u_rel_l2_vs_halfway"] = rel_l2(r["u"], plain["u"])
     lam = scipy.special.jn_zeros(0, 60)
@@ -448,8 +450,7 @@ def main():
                      "vs_f64": {st: {k: (round(v, 10) if isinstance(v, float) else v) for k, v in ps[st].items()}
                                 for st in ("f32", "f16s", "bf16s")}})
         note(f"precision study 40000 steps: {also[-1]['vs_f64']}")
-        # curved walls stream with pull: compared with the halfway pull run
-        also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, pull_run))
+        also.append(curved_bench(torch, lbm, case, args.storage, args.warmup, args.steps, main_run, pull_run))
         note(f"curved walls: {also[-1]['mlups']:.1f} MLUPS, pipe order {also[-1]['pipe_order']}")
         # SRT comparator: its step rate on the same run, and the stability sweep
         r = run_form(torch, lbm, dataclasses.replace(case, collision="srt2"), args.storage, args.warmup,

@@ -249,6 +249,9 @@ int prepare_links(lbm_domain* d) {
 bool lbm_domain::use_inplace() const {
     if (stream_mode == LBM_STREAM_PULL) return false;
     if (stream_mode == LBM_STREAM_INPLACE) return true;
+    // curved walls step faster with pull (their in-place kinds need the
+    // wall links in both kinds and the own-value records)
+    if (!crec.empty()) return false;
     // 4- and 8-byte populations whose two pull buffers no longer stay in the
     // Infinity Cache, while one buffer is small enough for it to serve part
     // of the in-place traffic
