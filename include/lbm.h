@@ -295,8 +295,9 @@ int lbm_monitors(lbm_domain* dom, double out[10]);
  * conversion from the storage type.  Asynchronous. */
 int lbm_read_populations(lbm_domain* dom, double* f_dev);
 
-/* Checkpoint: raw state (populations in storage format and in this build's
- * device layout, the open-boundary terms, time).  With host == NULL, *bytes
+/* Checkpoint: raw state (populations in storage format and in the library's
+ * pull layout, the open-boundary terms, time; a domain streamed in place is
+ * brought back to that layout first).  With host == NULL, *bytes
  * receives the size; otherwise *bytes must be at least that size.
  * Synchronizes the stream. */
 int lbm_get_state(lbm_domain* dom, void* host, size_t* bytes);
