@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 def _gpu_u(case, storage, steps):
     from paper_2101_11107_amd import lbm
     dom = lbm.Domain(case, storage=storage)
+    print(f"  {storage}: {'in place' if dom.in_place() else 'pull'}", flush=True)
     dom.init()
     dom.step(steps)
     rho, u = dom.moments()
@@ -61,14 +62,18 @@ def test_aneurysm256_20000_steps_against_oracle():
 
 @pytest.mark.slow
 def test_aneurysm512_f64_prefix_against_oracle():
+    """The 512^3 geometry over a 2000-step prefix: FP64 (pull) and FP32 (the
+    bench's configuration, streamed in place by the automatic choice)."""
     case = synth.aneurysm_case(512, seed=0)
     steps = 2000
-    print(f"case aneurysm512 f64 {steps}-step prefix against the oracle", flush=True)
-    rho, u = _gpu_u(case, "f64", steps)
+    print(f"case aneurysm512 f64 and f32 {steps}-step prefix against the oracle", flush=True)
+    got = {st: _gpu_u(case, st, steps) for st in ("f64", "f32")}
     rho_ref, u_ref = _oracle_u(case, steps, chunk=250)
-    e_u, e_rho = eps_u(u, u_ref), float(np.max(np.abs(rho - rho_ref)))
-    print(f"  f64: eps_u {e_u:.3e}  max |rho - rho_ref| {e_rho:.3e}", flush=True)
-    assert e_u < 1e-12 and e_rho < 1e-12
+    for st, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        rho, u = got[st]
+        e_u, e_rho = eps_u(u, u_ref), float(np.max(np.abs(rho - rho_ref)))
+        print(f"  {st}: eps_u {e_u:.3e}  max |rho - rho_ref| {e_rho:.3e}", flush=True)
+        assert e_u < tol and e_rho < tol
 
 
 # Bounds of each storage form against the FP64 run after five periods
