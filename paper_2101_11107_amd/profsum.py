@@ -254,9 +254,47 @@ def step_stats_for(trace_dir: str, patterns) -> tuple:
     return rows, None, None
 
 
+def summarize_valu(runs, nodes: int, last: int, cmd: str) -> str:
+    """Vector-instruction counts and VALU utilisation of the step kernel, per
+    kernel variant, from one counter run per label (runs: [(label, dir)]).
+    SQ_INSTS_VALU counts wavefront instructions; utilisation is
+    SQ_ACTIVE_INST_VALU / 256 CUs / (GRBM_GUI_ACTIVE / 8 XCDs)."""
+    waves = (nodes + 63) // 64
+    out = [f"# rocprofv3 counter summary: D3Q27 CHM-MRT step kernel (k_step), workload aneurysm512 "
+           f"({nodes} fluid nodes, {waves} wavefronts of 64 nodes)",
+           f"# command: rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES GRBM_GUI_ACTIVE "
+           f"--output-format csv -d <dir>/<label> -o run -- {cmd}",
+           f"# summary command: python -m paper_2101_11107_amd.profsum --valu-run <label>=<dir>/<label> ... "
+           f"--nodes {nodes}{f' --last {last}' if last else ''} --cmd \"<the command>\" --out <this file>",
+           "# per-dispatch means" + (f" over the last {last} step launches" if last else "") +
+           "; GRBM_GUI_ACTIVE is summed over the 8 XCDs (one XCD's count is the kernel's cycles)",
+           "# VALU utilisation = SQ_ACTIVE_INST_VALU / 256 CUs / (GRBM_GUI_ACTIVE / 8): issue cycles of one VALU "
+           "instruction per CU cycle; kernel times under counter collection run a few per cent above the trace's"]
+    for label, d in runs:
+        disp = {}
+        with open(_one(os.path.join(d, "**", "*counter_collection.csv"))) as fh:
+            for r in csv.DictReader(fh):
+                if STEP not in r["Kernel_Name"]:
+                    continue
+                e = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+                e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        ids = sorted(disp)[-last:] if last > 0 else sorted(disp)
+        by = {}
+        for k in ids:
+            by.setdefault(disp[k]["name"], []).append(disp[k])
+        for name, rows in sorted(by.items(), key=lambda kv: -len(kv[1])):
+            mean = {c: sum(r.get(c, 0.0) for r in rows) / len(rows)
+                    for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE")}
+            cyc = mean["GRBM_GUI_ACTIVE"] / 8.0
+            out.append(f"#   {label:12s} {_short(name).replace('void lbm::', '')[:58]:58s} dispatches {len(rows):4d}  "
+                       f"-> {mean['SQ_INSTS_VALU'] / waves:6.0f} VALU instructions per wavefront, VALU utilisation "
+                       f"{mean['SQ_ACTIVE_INST_VALU'] / 256.0 / cyc:.3f}, kernel {cyc / 2.4e3:.1f} us at 2.4 GHz")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--dir", required=True)
+    ap.add_argument("--dir", default=None, help="the three runs of the step summary, or the kernel runs")
     ap.add_argument("--storage", choices=list(POP_BYTES))
     ap.add_argument("--workload")
     ap.add_argument("--kernels", default=None,
@@ -268,10 +306,15 @@ def main():
                     help="step kernel: average only the last N launches (the bench's warm-up and timed steps)")
     ap.add_argument("--conv-flops", default=None,
                     help="train_steps,crop_coarse_voxels,forwards,grid_coarse_voxels: add the convolution efficiency")
+    ap.add_argument("--valu-run", action="append", default=[],
+                    help="label=dir: VALU summary of the step kernel from that counter run (repeatable)")
+    ap.add_argument("--nodes", type=int, default=0, help="fluid nodes (VALU summary)")
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.kernels:
+    if a.valu_run:
+        text = summarize_valu([tuple(r.split("=", 1)) for r in a.valu_run], a.nodes, a.last, a.cmd)
+    elif a.kernels:
         runs = [tuple(r.split("=", 1)) for r in a.pmc_run]
         text = summarize_kernels(a.dir, a.kernels.split(","), a.copy_mib, a.cmd, runs)
         if a.conv_flops:
