@@ -106,6 +106,7 @@ lbm::StepArgs make_args(const lbm_domain* d) {
     // in-place streaming reads and writes one buffer
     a.fout = d->layout != LAYOUT_PULL ? in : base + (in_a ? d->off_popB : d->off_popA);
     a.node = (const uint32_t*)(base + d->off_node);
+    a.wave_special = (const uint32_t*)(base + d->off_wspec);
     a.rowtab = (const lbm::RowEntry*)(base + d->off_rowtab);
     a.spec = (const SpecialNode*)(base + d->off_spec);
     a.link_meta = (const int32_t*)(base + d->off_lmeta);
@@ -623,6 +624,10 @@ int create_domain(const uint8_t* mask, int nx, int ny, int nz, unsigned periodic
         d->off_popA = take(d->pop_bytes);
         d->off_popB = take(d->pop_bytes);
         d->off_node = take((size_t)npad * 4);
+        d->wave_special.assign((size_t)npad / 64, 0u);
+        for (int64_t k = 0; k < npad; ++k)
+            if (d->node_words[(size_t)k] & lbm::SPECIAL_BIT) d->wave_special[(size_t)(k / 64)] = 1u;
+        d->off_wspec = take(d->wave_special.size() * 4);
         d->off_rowtab = take(d->rowtab.size() * sizeof(lbm::RowEntry) + 16);
         d->off_spec = take(std::max<size_t>(1, d->spec.size()) * sizeof(SpecialNode));
         const size_t nl = std::max<size_t>(1, d->nlinks());
@@ -782,6 +787,8 @@ int lbm_attach_device(lbm_domain* d, void* dev_ptr, size_t bytes) {
     HIP_TRY(lbm::launch_fill_zero(d->dev, d->dev_bytes, st), "clearing device memory");
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_node, d->node_words.data(), d->node_words.size() * 4,
                            hipMemcpyHostToDevice, st), "upload of node table");
+    HIP_TRY(hipMemcpyAsync(d->dev + d->off_wspec, d->wave_special.data(), d->wave_special.size() * 4,
+                           hipMemcpyHostToDevice, st), "upload of special-chunk flags");
     HIP_TRY(hipMemcpyAsync(d->dev + d->off_rowtab, d->rowtab.data(), d->rowtab.size() * sizeof(lbm::RowEntry),
                            hipMemcpyHostToDevice, st), "upload of row table");
     if (!d->spec.empty())

@@ -735,9 +735,18 @@ __device__ __forceinline__ void step_block(const StepArgs& a, int lb) {
 #pragma unroll
             for (int al = 0; al < 27; ++al) f[al] = ldp<S>(fin + dir_off(al), own0);
         }
-        const uint32_t w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
         const LBM_GLOBAL SpecialNode* sp = nullptr;
         const bool curved = CURVED && a.crec != nullptr;
+        uint32_t w;
+        if (IP == STREAM_LOCAL && !MON) {
+            // the node-local step needs a node's descriptor only for special
+            // nodes (and curved walls): a wavefront without any skips it
+            const uint32_t chunk = __builtin_amdgcn_readfirstlane((uint32_t)i / 64u);
+            const bool any = ((const LBM_GLOBAL uint32_t*)a.wave_special)[chunk] != 0u;
+            w = (any || curved) ? ((const LBM_GLOBAL uint32_t*)a.node)[i] : 0u;
+        } else {
+            w = ((const LBM_GLOBAL uint32_t*)a.node)[i];
+        }
         // in-place neighbour step: where each direction was read
         uint32_t loc[27];
         if (!(w & SPECIAL_BIT)) {

@@ -56,6 +56,7 @@ struct lbm_domain {
     int nblocks = 0, blocks_per_xcd = 0;
     int row_tile = 0;                      // row-tile edge of the node order
     std::vector<uint32_t> node_words;      // [npad]
+    std::vector<uint32_t> wave_special;    // [npad / 64] chunks holding a special node
     std::vector<lbm::RowEntry> rowtab;     // [rows][W]
     std::vector<lbm::SpecialNode> spec;
     std::vector<int32_t> spec_plane;       // [nspec][27] plane of each pulled value
@@ -84,7 +85,7 @@ struct lbm_domain {
     size_t dev_bytes = 0;
     size_t off_popA = 0, off_popB = 0, off_node = 0, off_rowtab = 0, off_spec = 0, off_lmeta = 0,
            off_lcoef = 0, off_ladd = 0, off_tcount = 0, off_trig = 0, off_part = 0, off_monout = 0, off_avg = 0,
-           off_probe = 0, off_crec = 0, off_cbase = 0, off_cside = 0;
+           off_probe = 0, off_crec = 0, off_cbase = 0, off_cside = 0, off_wspec = 0;
     size_t pop_bytes = 0;
 
     // cur: time-counter slot of the next step, toggled by every step.  The

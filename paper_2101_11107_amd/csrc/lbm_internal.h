@@ -94,6 +94,7 @@ struct StepArgs {
     const void* fin;             // post-collision populations of time t (pop_index layout, npad nodes)
     void* fout;                  // post-collision populations of time t+1
     const uint32_t* node;        // [npad] descriptor words
+    const uint32_t* wave_special; // [npad / 64] non-zero where the 64-node chunk holds a special node
     const RowEntry* rowtab;      // [rows][W]
     const SpecialNode* spec;     // [nspec]
     const int32_t* link_meta;    // [nlinks]
