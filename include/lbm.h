@@ -336,19 +336,25 @@ int lbm_batch_attach_device(lbm_batch* batch, void* dev_ptr, size_t bytes);
 
 /* Execution choice: cfg = { mode (0: one launch per step over the domains of
  * a group; 1: persistent launch looping over the group's work with a
- * device-wide barrier between steps), work-group size (128, 256 or 512),
- * streaming stores (0/1; 4- and 8-byte storage only), persistent grid (0 =
- * every work-group that fits at once), group budget in MiB (0: all domains
- * form one group; otherwise the domains are split into as many groups of
- * consecutive domains as the total population working set divided by the
- * budget, rounded up, with near-equal working sets, and each group runs all
- * requested steps before the next, which keeps it in the device cache) }.
- * EINVAL for other values. */
+ * device-wide barrier between steps; 2: one launch per step, every domain
+ * streamed in place in one buffer, as lbm_set_streaming(LBM_STREAM_INPLACE)
+ * steps it; needs work-group size 256 and no streaming stores, and
+ * lbm_batch_step fails with EINVAL while a domain has curved-wall links),
+ * work-group size (128, 256 or 512), streaming stores (0/1; 4- and 8-byte
+ * storage only), persistent grid (0 = every work-group that fits at once),
+ * group budget in MiB (0: all domains form one group; otherwise the domains
+ * are split into as many groups of consecutive domains as the total
+ * population working set (two buffers per domain, one in mode 2) divided by
+ * the budget, rounded up, with near-equal working sets, and each group runs
+ * all requested steps before the next, which keeps it in the device cache) }.
+ * EINVAL for other values.  Mode 2 leaves the domains in an in-place layout:
+ * readers of the state and lbm_step restore what they need first. */
 int lbm_batch_config(const lbm_batch* batch, int cfg[5]);
 int lbm_batch_set_config(lbm_batch* batch, const int cfg[5]);
 
 /* Autotuner: time every configuration on this batch for about trial_steps
- * steps each (the domains advance by those steps) and keep the fastest;
+ * steps each (the domains advance by those steps; mode 2 only without curved
+ * walls) and keep the fastest;
  * results are cached per process by storage, collision form, batch size
  * class and domain count.  best_ms_per_step (nullable) receives the best
  * time per step; when it is non-NULL the trials run even on a cache hit. */

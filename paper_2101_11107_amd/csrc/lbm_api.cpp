@@ -280,6 +280,14 @@ int sync_pull(lbm_domain* d) {
     return LBM_OK;
 }
 
+int enter_inplace(lbm_domain* d) {
+    const lbm::StepArgs a = make_args(d);
+    // curved walls: the blend's own values start from the pull layout
+    HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, !d->crec.empty(), d->stream), "in-place layout");
+    d->layout = LAYOUT_REVERSED;
+    return LBM_OK;
+}
+
 }  // namespace lbm_host
 
 namespace {
@@ -331,15 +339,6 @@ int build_graph(lbm_domain* d) {
     hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     d->graph[key] = ex;
-    return LBM_OK;
-}
-
-// Pull layout -> reversed layout, in place (the first in-place step reads it).
-int enter_inplace(lbm_domain* d) {
-    const lbm::StepArgs a = make_args(d);
-    // curved walls: the blend's own values start from the pull layout
-    HIP_TRY(lbm::launch_inplace_reverse(d->storage, a, !d->crec.empty(), d->stream), "in-place layout");
-    d->layout = LAYOUT_REVERSED;
     return LBM_OK;
 }
 
@@ -937,6 +936,11 @@ int lbm_step(lbm_domain* d, int nsteps) {
     if (rc) return rc;
     if (nsteps > 0 && d->use_inplace() && d->layout == LAYOUT_PULL) {
         rc = enter_inplace(d);
+        if (rc) return rc;
+    }
+    // an in-place batch may have left a pull domain in an in-place layout
+    if (nsteps > 0 && !d->use_inplace() && d->layout != LAYOUT_PULL) {
+        rc = sync_pull(d);
         if (rc) return rc;
     }
     int left = nsteps;

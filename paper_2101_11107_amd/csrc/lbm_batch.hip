@@ -5,7 +5,9 @@
 //  - k_batch_persistent: one launch for K steps; the work-groups loop over the
 //    work items and meet at a device-wide barrier between steps.
 // Both call the same per-block step as the single-domain kernel, so each
-// domain's populations are bit-identical to stepping it alone.
+// domain's populations are bit-identical to stepping it alone.  Per-step
+// launches also stream in place: every domain of the group holds one buffer
+// in the same in-place layout, and the host names the kind of each launch.
 #include "lbm_device.h"
 
 #include <type_traits>
@@ -16,10 +18,12 @@ namespace {
 // Bound of a barrier wait (iterations of a ~100-cycle sleep, about 0.2 s).
 constexpr unsigned SPIN_LIMIT = 1u << 21;
 
-template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR>
+template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR, int IP = STREAM_PULL>
 __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int step) {
     const int packed = b.item_map[item];
     StepArgs a = b.doms[packed >> ITEM_DOMAIN_SHIFT];
+    // odd steps: the other time slot (pull: and the other buffer; in place
+    // the two pointers are the same buffer)
     if (step & 1) {
         const void* t = a.fin;
         a.fin = a.fout;
@@ -32,24 +36,24 @@ __device__ __forceinline__ void batch_item(const BatchArgs& b, int item, int ste
     // domain's own step would (the forms round differently).
     const bool one = ONE || (a.collision == 0 && a.s[1] == 1.0 && a.s[2] == 1.0 && a.s[3] == 1.0 && a.s[4] == 1.0);
     if (one) {
-        if (a.periodic & 6) step_block<S, MON, 1, true, NT, BS, CUR>(a, lb);
-        else step_block<S, MON, 1, false, NT, BS, CUR>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 1, true, NT, BS, CUR, IP>(a, lb);
+        else step_block<S, MON, 1, false, NT, BS, CUR, IP>(a, lb);
     } else if (a.collision == 1) {
-        if (a.periodic & 6) step_block<S, MON, 2, true, NT, BS, CUR>(a, lb);
-        else step_block<S, MON, 2, false, NT, BS, CUR>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 2, true, NT, BS, CUR, IP>(a, lb);
+        else step_block<S, MON, 2, false, NT, BS, CUR, IP>(a, lb);
     } else {
-        if (a.periodic & 6) step_block<S, MON, 0, true, NT, BS, CUR>(a, lb);
-        else step_block<S, MON, 0, false, NT, BS, CUR>(a, lb);
+        if (a.periodic & 6) step_block<S, MON, 0, true, NT, BS, CUR, IP>(a, lb);
+        else step_block<S, MON, 0, false, NT, BS, CUR, IP>(a, lb);
     }
 }
 
-template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR>
+template <class S, bool MON, bool ONE, bool NT, int BS, bool CUR, int IP = STREAM_PULL>
 __global__ __launch_bounds__(BS) void k_batch_step(BatchArgs b, int step) {
     // XCD-aware order as in the single-domain kernel
     const int hb = blockIdx.x;
     const int item = (hb & 7) * b.items_per_xcd + (hb >> 3);
     if (item >= b.nitems) return;
-    batch_item<S, MON, ONE, NT, BS, CUR>(b, item, step);
+    batch_item<S, MON, ONE, NT, BS, CUR, IP>(b, item, step);
 }
 
 // Device-wide barrier for epoch e (1, 2, ... within one launch; the host clears
@@ -122,13 +126,20 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs b, int step0,
 // (6 x 26000 B fits the CU's 160 KiB, 7 x does not).
 constexpr unsigned BATCH_LDS_SIX_PER_CU = 26000;
 
-template <class S, bool ONE, bool NT, int BS, bool CUR>
+template <class S, bool ONE, bool NT, int BS, bool CUR, int IP = STREAM_PULL>
 hipError_t step_bs(const BatchArgs& b, int step, bool monitor, hipStream_t st) {
     const dim3 grid(8 * b.items_per_xcd), block(BS);
     const unsigned lds = (NT && sizeof(S) == 4 && BS == 256) ? BATCH_LDS_SIX_PER_CU : 0u;
-    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS, CUR>), grid, block, lds, st, b, step);
-    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS, CUR>), grid, block, lds, st, b, step);
+    if (monitor) hipLaunchKernelGGL((k_batch_step<S, true, ONE, NT, BS, CUR, IP>), grid, block, lds, st, b, step);
+    else hipLaunchKernelGGL((k_batch_step<S, false, ONE, NT, BS, CUR, IP>), grid, block, lds, st, b, step);
     return hipGetLastError();
+}
+
+// In-place launches: 256 threads, cached stores, no curved-wall blend.
+template <class S, bool ONE>
+hipError_t step_inplace_one(int kind, const BatchArgs& b, int step, bool monitor, hipStream_t st) {
+    if (kind & BATCH_IP_LOCAL) return step_bs<S, ONE, false, 256, false, STREAM_LOCAL>(b, step, monitor, st);
+    return step_bs<S, ONE, false, 256, false, STREAM_NEIGHBOUR>(b, step, monitor, st);
 }
 
 template <class S, bool ONE, bool NT, int BS, bool CUR>
@@ -190,6 +201,12 @@ hipError_t capacity_one(const BatchConfig& c, int* blocks) {
 
 template <class S>
 hipError_t step_s(int kind, const BatchArgs& b, const BatchConfig& c, int step, bool monitor, hipStream_t st) {
+    if (kind & (BATCH_IP_NEIGHBOUR | BATCH_IP_LOCAL)) {
+        if (c.mode != BATCH_MODE_INPLACE || c.block != 256 || c.stream_store || (kind & BATCH_CURVED))
+            return hipErrorInvalidValue;
+        return (kind & BATCH_RATES_ONE) ? step_inplace_one<S, true>(kind, b, step, monitor, st)
+                                        : step_inplace_one<S, false>(kind, b, step, monitor, st);
+    }
     BATCH_KIND(step_one, b, c, step, monitor, st)
 }
 

@@ -40,11 +40,12 @@ struct lbm_batch {
     std::vector<lbm::StepArgs> args_host;
     std::vector<int> items_host;
     std::vector<int> built_parity;    // each domain's buffer parity when args_host was built
-    int built_block = 0, built_group_mb = -1;
+    int built_block = 0, built_group_mb = -1, built_mode = -1;
+    int built_layout = -1;             // the domains' layout when args_host was built
 
     lbm::BatchConfig cfg{0, 256, 0, 0, 0};
     std::vector<hipGraphExec_t> graphs;   // per group: GRAPH_STEPS steps with cfg
-    int graph_cfg[6] = {-1, -1, -1, -1, -1, -1};
+    int graph_cfg[7] = {-1, -1, -1, -1, -1, -1, -1};
     int error_host = 0;
 
     void drop_graph() {
@@ -71,16 +72,36 @@ lbm::BatchArgs batch_args(const lbm_batch* b, int g) {
     return a;
 }
 
-// Bring the device tables up to date with the domains' parities and the block
-// size of the current configuration.
+// Bring every domain to the layout the configuration steps: the pull layout,
+// or one in-place layout shared by all domains (kept when they already share
+// one, else every domain enters the reversed layout from the pull layout).
+// The conversions run on the domains' streams, after the batch's own earlier
+// work has finished.
+int align_layouts(lbm_batch* b) {
+    const bool inplace = b->cfg.mode == lbm::BATCH_MODE_INPLACE;
+    const int l0 = b->doms[0]->layout;
+    bool same = inplace ? l0 != LAYOUT_PULL : l0 == LAYOUT_PULL;
+    for (const lbm_domain* d : b->doms) same = same && d->layout == l0;
+    if (same) return LBM_OK;
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch stream synchronize");
+    for (lbm_domain* d : b->doms) {
+        int rc = sync_pull(d);
+        if (rc == LBM_OK && inplace) rc = enter_inplace(d);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+// Bring the device tables up to date with the domains' parities and layouts
+// and the block size of the current configuration.
 int refresh_tables(lbm_batch* b) {
-    bool stale = b->built_block != b->cfg.block || b->built_parity.size() != b->doms.size();
+    int rc = align_layouts(b);
+    if (rc) return rc;
+    bool stale = b->built_block != b->cfg.block || b->built_parity.size() != b->doms.size() ||
+                 b->built_mode != b->cfg.mode || b->built_layout != b->doms[0]->layout;
     for (size_t k = 0; !stale && k < b->doms.size(); ++k) stale = b->built_parity[k] != b->doms[k]->cur;
     for (lbm_domain* d : b->doms) {
         if (d->links_dirty) stale = true;
-        // the batch kernels step the pull layout
-        int rc = sync_pull(d);
-        if (rc) return rc;
         rc = prepare_links(d);
         if (rc) return rc;
         // the domain's own stream may hold its uploads; the batch runs on its own stream
@@ -96,12 +117,14 @@ int refresh_tables(lbm_batch* b) {
     if (!stale) return LBM_OK;
     const int bs = b->cfg.block;
     // Groups of consecutive domains: as many as the working-set budget asks
-    // for (both population buffers of each domain), with boundaries at the
-    // domain edges closest to equal shares, so no group is left small (a
-    // small launch runs below the bandwidth of a large one).
+    // for (the population buffers each domain steps: two with pull, one in
+    // place), with boundaries at the domain edges closest to equal shares, so
+    // no group is left small (a small launch runs below the bandwidth of a
+    // large one).
     const size_t nd = b->doms.size();
+    const double buffers = b->cfg.mode == lbm::BATCH_MODE_INPLACE ? 1.0 : 2.0;
     std::vector<double> cum(nd + 1, 0.0);
-    for (size_t k = 0; k < nd; ++k) cum[k + 1] = cum[k] + 2.0 * (double)b->doms[k]->pop_bytes;
+    for (size_t k = 0; k < nd; ++k) cum[k + 1] = cum[k] + buffers * (double)b->doms[k]->pop_bytes;
     const double budget = b->cfg.group_mb > 0 ? (double)((size_t)b->cfg.group_mb << 20) : 0.0;
     const size_t ngroups = budget > 0.0 ? std::min(nd, (size_t)std::ceil(cum[nd] / budget)) : 1;
     b->group_first.assign(1, 0);
@@ -135,6 +158,8 @@ int refresh_tables(lbm_batch* b) {
     }
     b->built_block = bs;
     b->built_group_mb = b->cfg.group_mb;
+    b->built_mode = b->cfg.mode;
+    b->built_layout = b->doms[0]->layout;
     b->drop_graph();
     HIP_TRY(hipMemcpyAsync(b->dev + b->off_args, b->args_host.data(), b->args_host.size() * sizeof(lbm::StepArgs),
                            hipMemcpyHostToDevice, b->stream), "batch table upload");
@@ -153,10 +178,21 @@ int batch_kind(const lbm_batch* b) {
 }
 
 // Enqueue nsteps (>= 1) steps of group g with the current configuration; the
-// last one accumulates the group's monitors.
+// last one accumulates the group's monitors.  In place, the kinds alternate
+// from the layout the tables were built at (reversed: the neighbour kind
+// first).
 int enqueue_steps(lbm_batch* b, int g, int nsteps) {
     const lbm::BatchArgs a = batch_args(b, g);
-    if (b->cfg.mode == 1 && nsteps > 1) {
+    if (b->cfg.mode == lbm::BATCH_MODE_INPLACE) {
+        const bool rev0 = b->built_layout == LAYOUT_REVERSED;
+        for (int s = 0; s < nsteps; ++s) {
+            const int ip = (rev0 == ((s & 1) == 0)) ? lbm::BATCH_IP_NEIGHBOUR : lbm::BATCH_IP_LOCAL;
+            HIP_TRY(lbm::launch_batch_step(b->storage, batch_kind(b) | ip, a, b->cfg, s, s == nsteps - 1, b->stream),
+                    "batch step kernel");
+        }
+        return LBM_OK;
+    }
+    if (b->cfg.mode == lbm::BATCH_MODE_PERSISTENT && nsteps > 1) {
         // barrier epochs restart at 1 in every launch
         HIP_TRY(lbm::launch_fill_zero(a.barrier, lbm::BARRIER_WORDS * sizeof(unsigned), b->stream),
                 "barrier reset");
@@ -173,8 +209,8 @@ int enqueue_steps(lbm_batch* b, int g, int nsteps) {
 }
 
 int ensure_graphs(lbm_batch* b) {
-    const int key[6] = {b->cfg.mode, b->cfg.block, b->cfg.stream_store, b->cfg.grid, b->cfg.group_mb,
-                        batch_kind(b)};
+    const int key[7] = {b->cfg.mode, b->cfg.block, b->cfg.stream_store, b->cfg.grid, b->cfg.group_mb,
+                        batch_kind(b), b->built_layout};
     const int ng = (int)b->group_first.size() - 1;
     if ((int)b->graphs.size() == ng && std::memcmp(key, b->graph_cfg, sizeof key) == 0) return LBM_OK;
     b->drop_graph();
@@ -201,6 +237,11 @@ int ensure_graphs(lbm_batch* b) {
 void advance_domains(lbm_batch* b, int nsteps) {
     for (lbm_domain* d : b->doms) {
         d->cur ^= (nsteps & 1);
+        // in place: one buffer, and the layout turns with every step
+        if (d->layout != LAYOUT_PULL && (nsteps & 1)) {
+            d->pop_flip ^= 1;
+            d->layout = LAYOUT_REVERSED + LAYOUT_STREAMED - d->layout;
+        }
         d->t += nsteps;
         if (d->avg_track) d->avg_count += nsteps;
         d->monitored = true;
@@ -211,6 +252,8 @@ void advance_domains(lbm_batch* b, int nsteps) {
 // Each group runs all nsteps before the next group starts (the groups are
 // independent), so a group's populations stay in cache between its steps.
 int run_steps(lbm_batch* b, int nsteps) {
+    if (b->cfg.mode == lbm::BATCH_MODE_INPLACE && (batch_kind(b) & lbm::BATCH_CURVED))
+        return fail(LBM_EINVAL, "in-place batch stepping takes no curved walls");
     int rc = refresh_tables(b);
     if (rc) return rc;
     if (nsteps >= GRAPH_STEPS) {
@@ -234,10 +277,11 @@ int run_steps(lbm_batch* b, int nsteps) {
 }
 
 bool valid_config(const lbm_batch* b, const lbm::BatchConfig& c) {
-    if (c.mode != 0 && c.mode != 1) return false;
+    if (c.mode < lbm::BATCH_MODE_STEP || c.mode > lbm::BATCH_MODE_INPLACE) return false;
     if (c.block != 128 && c.block != 256 && c.block != 512) return false;
     if (c.stream_store != 0 && c.stream_store != 1) return false;
     if (c.stream_store && b->storage >= LBM_F16S) return false;
+    if (c.mode == lbm::BATCH_MODE_INPLACE && (c.block != 256 || c.stream_store)) return false;
     return c.grid >= 0 && c.group_mb >= 0;
 }
 
@@ -371,6 +415,10 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
                         cands.push_back({1, block, ns, -2, group_mb});   // half of the resident capacity
                     }
                 }
+    // in place: one buffer per domain, so a group of the same budget holds
+    // twice the nodes
+    if (!(batch_kind(b) & lbm::BATCH_CURVED))
+        for (int group_mb : {0, 96, 128, 192}) cands.push_back({lbm::BATCH_MODE_INPLACE, 256, 0, 0, group_mb});
     const int graphs = std::max(1, (trial_steps + GRAPH_STEPS - 1) / GRAPH_STEPS);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event create");

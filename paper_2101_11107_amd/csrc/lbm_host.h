@@ -155,7 +155,9 @@ lbm::StepArgs make_args(const lbm_domain* d);
 // Upload the open-boundary coefficients and inlet phase if they changed.
 int prepare_links(lbm_domain* d);
 // Bring an in-place domain's populations back to the pull layout (the layout
-// every reader of the state and the batch use); a no-op for the pull layout.
+// every reader of the state and the pull batch use); a no-op for the pull layout.
 int sync_pull(lbm_domain* d);
+// Pull layout -> reversed layout, in place (the first in-place step reads it).
+int enter_inplace(lbm_domain* d);
 
 }  // namespace lbm_host

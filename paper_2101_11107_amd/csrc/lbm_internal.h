@@ -166,7 +166,8 @@ struct BatchArgs {
 
 // Execution choices of a batch (picked by the autotuner).
 struct BatchConfig {
-    int mode;            // 0: one launch per step; 1: persistent launch with device-wide barriers
+    int mode;            // 0: one launch per step; 1: persistent launch with device-wide barriers;
+                         // 2: one launch per step, streamed in place (BATCH_MODE_INPLACE)
     int block;           // work-group size: 128, 256 or 512
     int stream_store;    // non-temporal population stores
     int grid;            // persistent mode: number of work-groups (0 = all that fit)
@@ -207,9 +208,13 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 
 // Batched launchers (lbm_batch.hip).  kind: BATCH_RATES_ONE when every domain
 // is CHM-MRT with free rates of one, | BATCH_CURVED when a domain has
-// curved-wall records; step: the step index within the launch sequence (its
-// parity selects the buffers); monitor: accumulate monitors.
-enum : int { BATCH_RATES_ONE = 1, BATCH_CURVED = 2 };
+// curved-wall records, | BATCH_IP_NEIGHBOUR or BATCH_IP_LOCAL for the
+// in-place kind of this launch (BATCH_MODE_INPLACE only, which takes 256
+// threads, cached stores and no curved walls); step: the step index within the
+// launch sequence (its parity selects the time slot and, for pull, the
+// buffers); monitor: accumulate monitors.
+enum : int { BATCH_RATES_ONE = 1, BATCH_CURVED = 2, BATCH_IP_NEIGHBOUR = 4, BATCH_IP_LOCAL = 8 };
+enum : int { BATCH_MODE_STEP = 0, BATCH_MODE_PERSISTENT = 1, BATCH_MODE_INPLACE = 2 };
 hipError_t launch_batch_step(int storage, int kind, const BatchArgs& b, const BatchConfig& c, int step,
                              bool monitor, hipStream_t stream);
 hipError_t launch_batch_persistent(int storage, int kind, const BatchArgs& b, const BatchConfig& c,
