@@ -182,7 +182,8 @@ def batch_bench(torch, lbm, steps, storage="f16s"):
             "steps": steps, "batched_mlups": round(total * steps / t_batch / 1e6, 1),
             "sequential_mlups": round(total * steps / t_seq / 1e6, 1),
             "batched_over_sequential": round(t_seq / t_batch, 3),
-            "autotuned_config": {"mode": ["launch_per_step", "persistent"][cfg[0]], "block": cfg[1],
+            "autotuned_config": {"mode": ["launch_per_step", "persistent", "launch_per_step_in_place"][cfg[0]],
+                                 "block": cfg[1],
                                  "stream_store": cfg[2], "grid": cfg[3], "group_mb": cfg[4], "row_tile": tile},
             "autotune_best_ms_per_step_by_row_tile": {str(k): round(v, 4) for k, v in tile_ms.items()},
             "autotune_best_ms_per_step": round(tuned_ms, 4),
