@@ -416,9 +416,11 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, double* best_ms_per_step) 
                     }
                 }
     // in place: one buffer per domain, so a group of the same budget holds
-    // twice the nodes
+    // twice the nodes; the best groups hold about 140-160 MiB of populations
+    // (measured), so the budgets step finely there
     if (!(batch_kind(b) & lbm::BATCH_CURVED))
-        for (int group_mb : {0, 96, 128, 192}) cands.push_back({lbm::BATCH_MODE_INPLACE, 256, 0, 0, group_mb});
+        for (int group_mb : {0, 96, 128, 144, 160, 176, 192})
+            cands.push_back({lbm::BATCH_MODE_INPLACE, 256, 0, 0, group_mb});
     const int graphs = std::max(1, (trial_steps + GRAPH_STEPS - 1) / GRAPH_STEPS);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event create");
